@@ -12,9 +12,11 @@ explicitly and excludes sketch generation from its timings).  The library and th
 share this contract, each implementing it from this description:
 
   key    = (seed, 0) for Philox4x64-10
-  row i of V (column i of S1):  y = Philox((i, 0, 0, 1), key)
-      bucket h(i) = floor(y0 * s1 / 2^64)            (high word of the 128-bit product)
-      sign   g(i) = -1 if bit 63 of y1 is set else +1
+  row i of V (column i of S1):  y = Philox((floor(i/4), 0, 0, 1), key), w = y[i mod 4]
+      (one generator block serves four consecutive rows)
+      bucket h(i) = floor(w * s1 / 2^64)             (high word of the 128-bit product)
+      sign   g(i) = -1 if bit 0 of w is set else +1  (the low bit is independent of the
+                                                      high bits that pick the bucket)
   entries S2[4b .. 4b+3, k]:     y = Philox((k, b, 0, 2), key)
       two Box-Muller pairs, (y0, y1) -> rows 4b, 4b+1 and (y2, y3) -> rows 4b+2, 4b+3:
       u1 = ((ya >> 11) + 1) * 2^-53  in (0, 1]
@@ -43,10 +45,12 @@ def countsketch_hash(m, s1, seed, row0=0):
     if s1 < 1:
         raise ValueError("s1 must be >= 1")
     rows = np.arange(row0, row0 + m, dtype=np.uint64)
-    y0, y1, _, _ = philox4x64(rows, 0, 0, TAG_COUNTSKETCH, seed, 0)
-    hi, _ = mulhilo64(y0, np.uint64(s1))
+    y = philox4x64(rows >> np.uint64(2), 0, 0, TAG_COUNTSKETCH, seed, 0)
+    lane = (rows & np.uint64(3)).astype(np.int64)
+    w = np.choose(lane, y) if m else np.zeros(0, dtype=np.uint64)
+    hi, _ = mulhilo64(w, np.uint64(s1))
     bucket = hi.astype(np.int64)
-    sign = np.where((y1 >> np.uint64(63)) != 0, -1, 1).astype(np.int8)
+    sign = np.where((w & np.uint64(1)) != 0, -1, 1).astype(np.int8)
     return bucket, sign
 
 
