@@ -1,0 +1,148 @@
+/*
+ * rcqr -- randomized Householder-Cholesky QR with multisketching on one AMD Instinct MI355X.
+ *
+ * Method: Higgins, Szyld, Boman, Yamazaki, "Analysis of Randomized Householder-Cholesky QR
+ * Factorization with Multisketching" (arXiv 2309.05868), Algorithm 3 (rand_cholQR) built on
+ * Algorithm 1 (randQR) and Algorithm 2 (cholQR).  Notation: V has m rows and n columns (the
+ * paper writes n rows and m columns); the CountSketch S1 has s1 rows, the Gaussian sketch S2
+ * has s2 rows.
+ *
+ * Data layout (all FP64, all row-major, all in device memory owned by the caller):
+ *   V  m x n, leading dimension ldv >= n      input, read three times, never written
+ *                                             (unless Q aliases it)
+ *   Q  m x n, leading dimension ldq >= n      output, orthonormal columns; may alias V
+ *                                             (d_Q == d_V with ldq == ldv)
+ *   R  n x n, leading dimension ldr >= n      output, upper triangular with positive
+ *                                             diagonal; the strict lower triangle is
+ *                                             written as zeros
+ *   workspace  rcqr_workspace_bytes() bytes   caller-allocated device memory, 256-byte
+ *                                             aligned; holds W1, W, R0, G, R1, partial sums,
+ *                                             the CountSketch bucket index and the status
+ *                                             word.  One plan uses it at a time.
+ *
+ * Sketch contract (the paper fixes no generator; Section 6.1 only says the sketches were
+ * built explicitly).  Philox4x64-10 (Salmon et al., SC'11), key (seed, 0):
+ *   row i:  y = Philox((floor(i/4), 0, 0, 1)), w = y[i mod 4],
+ *           bucket h(i) = floor(w s1 / 2^64), sign = -1 if (w & 1) else +1    (S1, Section 3)
+ *   S2[4b+t, k], t = 0..3:  y = Philox((k, b, 0, 2)); Box-Muller on (y0, y1) -> t = 0, 1 and
+ *           (y2, y3) -> t = 2, 3 with u1 = ((ya >> 11) + 1) 2^-53, u2 = (yb >> 11) 2^-53,
+ *           z = sqrt(-2 ln u1) {cos, sin}(2 pi u2);  S2[j, k] = z / sqrt(s2)        (Section 3)
+ *
+ * Errors: argument errors are returned synchronously.  Numerical failures are found on the
+ * device and reported through rcqr_info(): RCQR_E_RANK when the Householder R0 of the sketch
+ * has a zero or non-finite diagonal entry, RCQR_E_CHOL when the Cholesky factorization of
+ * the Gram matrix of V R0^{-1} meets a pivot that is not positive (NaN included).  After a
+ * numerical failure the contents of Q and R are unspecified.
+ *
+ * Streams and threads: every entry point that launches work enqueues it on the plan's HIP
+ * stream and returns without waiting, except rcqr_info() and rcqr_phase_times(), which wait
+ * for the stream.  A plan (and its workspace) must not be used by two host threads at once.
+ */
+#ifndef RCQR_H
+#define RCQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rcqr_plan_s* rcqr_plan_t;
+
+typedef enum {
+  RCQR_OK = 0,
+  RCQR_E_INVALID = 1,     /* bad argument (sizes, leading dimensions, null pointers, workspace) */
+  RCQR_E_UNSUPPORTED = 2, /* n > 128 */
+  RCQR_E_NOMEM = 3,       /* host allocation of the plan failed */
+  RCQR_E_HIP = 4,         /* a HIP runtime call failed (launch, event, copy) */
+  RCQR_E_RANK = 5,        /* Householder R0 of the sketch has a zero / non-finite diagonal */
+  RCQR_E_CHOL = 6         /* Cholesky of the Gram matrix met a non-positive pivot */
+} rcqr_status_t;
+
+/* Largest number of columns the kernels support. */
+#define RCQR_MAX_N 128
+
+/* Bytes of device workspace a plan of this shape needs (0 if the shape is invalid). */
+size_t rcqr_workspace_bytes(int64_t m, int64_t n, int64_t s1, int64_t s2, uint32_t flags);
+
+/*
+ * Create a plan for V of m x n with CountSketch size s1 and Gaussian sketch size s2
+ * (Algorithm 1's S1 of s1 x m and S2 of s2 x s1).  Requires 1 <= n <= 128, n <= m,
+ * n <= s2 <= s1, s1 < 2^31, m < 2^31; s1 > m is accepted (the sketch is then not
+ * compressive but still a CountSketch).  `stream` is a hipStream_t (NULL = default stream).
+ * The workspace must stay valid until rcqr_destroy().  flags: 0.
+ */
+rcqr_status_t rcqr_plan(rcqr_plan_t* plan, int64_t m, int64_t n, int64_t s1, int64_t s2, uint64_t seed,
+                        uint32_t flags, void* d_workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Algorithm 3 (rand_cholQR): W = S2 (S1 V); R0 = Householder R of W (Algorithm 1); Q0 = V R0^{-1}
+ * by row-wise substitution; G = Q0^T Q0; R1 = chol(G) (Algorithm 2); Q = Q0 R1^{-1};
+ * R = R1 R0.  Asynchronous on the plan's stream.
+ */
+rcqr_status_t rcqr_factor(rcqr_plan_t plan, const double* d_V, int64_t ldv, double* d_Q, int64_t ldq,
+                          double* d_R, int64_t ldr);
+
+/*
+ * Algorithm 4 (cholQR2) on the same plan and workspace, the comparator of Section 6: two
+ * passes of Cholesky QR, R = R1 R0.  Fails with RCQR_E_CHOL once kappa(V) is beyond about
+ * u^{-1/2} (Section 6.3).  Asynchronous on the plan's stream.
+ */
+rcqr_status_t rcqr_cholqr2(rcqr_plan_t plan, const double* d_V, int64_t ldv, double* d_Q, int64_t ldq,
+                           double* d_R, int64_t ldr);
+
+/* Wait for the plan's stream and report the last factorization: *status is an rcqr_status_t
+ * (RCQR_OK, RCQR_E_RANK or RCQR_E_CHOL), *column the 1-based failing column or 0. */
+rcqr_status_t rcqr_info(rcqr_plan_t plan, int32_t* status, int32_t* column);
+
+/* Free the host-side plan; does not touch the caller's memory. */
+rcqr_status_t rcqr_destroy(rcqr_plan_t plan);
+
+/* Static description of a status code. */
+const char* rcqr_status_string(int32_t status);
+
+/*
+ * Per-phase timing.  rcqr_set_timing(plan, steps) with steps > 0 makes every rcqr_factor call
+ * record HIP events on the plan's stream between its phases, into a ring of `steps` calls
+ * (steps = 0 turns timing off; at most 4096).  rcqr_phase_times() waits for the stream, writes
+ * the mean duration in milliseconds of up to `max` phases over the calls recorded since the
+ * previous rcqr_phase_times (the last `steps` of them), resets the count and returns the phase
+ * count through *count; rcqr_phase_name(i) names phase i.
+ * Phases: 0 countsketch (sketch generation and W1 = S1 V), 1 gaussian (W = S2 W1),
+ * 2 householder (R0), 3 trsm_gram (Q0 = V R0^{-1}, partial G), 4 cholesky (G, R1, R = R1 R0),
+ * 5 final (Q = Q0 R1^{-1}, recomputing Q0).
+ */
+rcqr_status_t rcqr_set_timing(rcqr_plan_t plan, int32_t steps);
+rcqr_status_t rcqr_phase_times(rcqr_plan_t plan, float* ms, int32_t max, int32_t* count);
+const char* rcqr_phase_name(int32_t phase);
+
+/* ------------------------------------------------------------------------------------------
+ * Inspection entry points (same library; used by tests, never on a timed path).
+ * ------------------------------------------------------------------------------------------ */
+
+/* CountSketch bucket h(i) and sign (+1/-1) of rows row0 .. row0+count-1 under the plan's seed
+ * and s1 (Section 3's S1).  d_bucket: count int32, d_sign: count int8, device memory. */
+rcqr_status_t rcqr_sketch_hash(rcqr_plan_t plan, int64_t row0, int64_t count, int32_t* d_bucket, int8_t* d_sign);
+
+/* Entries S2[j0 .. j0+nj-1, k0 .. k0+nk-1] of the Gaussian sketch (Section 3), row-major with
+ * leading dimension nk, into device memory d_out (nj * nk doubles). */
+rcqr_status_t rcqr_gaussian_block(rcqr_plan_t plan, int64_t j0, int64_t nj, int64_t k0, int64_t nk, double* d_out);
+
+/* Copy the intermediates of the last rcqr_factor call from the workspace (device to device):
+ * W1 (s1 x n), W (s2 x n), R0 (n x n), G (n x n, upper triangle; lower set to zero),
+ * R1 (n x n).  Any pointer may be NULL. */
+rcqr_status_t rcqr_intermediates(rcqr_plan_t plan, double* d_W1, double* d_W, double* d_R0, double* d_G,
+                                 double* d_R1);
+
+/* Q0 = V R0^{-1} as computed inside the Gram pass (d_Q0_gram) and as recomputed inside the
+ * final pass (d_Q0_final), using R0 of the last rcqr_factor call on the same V.  The method
+ * relies on the two being bitwise identical.  Both outputs m x n with leading dimension ldq. */
+rcqr_status_t rcqr_q0_twice(rcqr_plan_t plan, const double* d_V, int64_t ldv, double* d_Q0_gram,
+                            double* d_Q0_final, int64_t ldq);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RCQR_H */

@@ -1,0 +1,233 @@
+"""rcqr: randomized Householder-Cholesky QR with multisketching on one AMD MI355X (gfx950).
+
+Thin binding over the C ABI in include/rcqr.h (librcqr.so, built in-tree by
+``python -m paper_2309_05868_amd.build``).  This module only marshals arguments: every step of
+the factorization runs in the library's HIP kernels.  PyTorch provides device memory and the
+stream.  There is no CPU fallback: without the built library (or without a GPU) the calls fail.
+
+Method: Higgins, Szyld, Boman, Yamazaki, arXiv 2309.05868, Algorithm 3 (rand_cholQR).
+"""
+
+import ctypes
+import os
+import re
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librcqr.so")
+HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "rcqr.h")
+
+OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_HIP, E_RANK, E_CHOL = range(7)
+MAX_N = 64  # columns the current kernels accept (the ABI reserves up to 128)
+
+_lib = None
+
+_c_i64, _c_u64, _c_i32, _c_u32, _c_p = ctypes.c_int64, ctypes.c_uint64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_void_p
+
+_SIGNATURES = {
+    "rcqr_workspace_bytes": (ctypes.c_size_t, [_c_i64, _c_i64, _c_i64, _c_i64, _c_u32]),
+    "rcqr_plan": (_c_i32, [ctypes.POINTER(_c_p), _c_i64, _c_i64, _c_i64, _c_i64, _c_u64, _c_u32, _c_p, ctypes.c_size_t, _c_p]),
+    "rcqr_factor": (_c_i32, [_c_p, _c_p, _c_i64, _c_p, _c_i64, _c_p, _c_i64]),
+    "rcqr_cholqr2": (_c_i32, [_c_p, _c_p, _c_i64, _c_p, _c_i64, _c_p, _c_i64]),
+    "rcqr_info": (_c_i32, [_c_p, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32)]),
+    "rcqr_destroy": (_c_i32, [_c_p]),
+    "rcqr_status_string": (ctypes.c_char_p, [_c_i32]),
+    "rcqr_set_timing": (_c_i32, [_c_p, _c_i32]),
+    "rcqr_phase_times": (_c_i32, [_c_p, ctypes.POINTER(ctypes.c_float), _c_i32, ctypes.POINTER(_c_i32)]),
+    "rcqr_phase_name": (ctypes.c_char_p, [_c_i32]),
+    "rcqr_sketch_hash": (_c_i32, [_c_p, _c_i64, _c_i64, _c_p, _c_p]),
+    "rcqr_gaussian_block": (_c_i32, [_c_p, _c_i64, _c_i64, _c_i64, _c_i64, _c_p]),
+    "rcqr_intermediates": (_c_i32, [_c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
+    "rcqr_q0_twice": (_c_i32, [_c_p, _c_p, _c_i64, _c_p, _c_p, _c_i64]),
+}
+
+
+class RcqrError(RuntimeError):
+    def __init__(self, status, what, column=0):
+        self.status = int(status)
+        self.column = int(column)
+        msg = f"{what}: {status_string(status)} (status {status}"
+        msg += f", column {column})" if column else ")"
+        super().__init__(msg)
+
+
+def declared_functions(header=HEADER_PATH):
+    """Names of the functions include/rcqr.h declares."""
+    with open(header) as f:
+        text = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
+    return sorted(set(re.findall(r"\b(rcqr_\w+)\s*\(", text)))
+
+
+def lib():
+    """The loaded librcqr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2309_05868_amd.build`")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def status_string(status):
+    return lib().rcqr_status_string(int(status)).decode()
+
+
+def _check(status, what):
+    if status != OK:
+        raise RcqrError(status, what)
+
+
+def workspace_bytes(m, n, s1, s2):
+    return int(lib().rcqr_workspace_bytes(m, n, s1, s2, 0))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check_matrix(V, m, n, name):
+    if not isinstance(V, torch.Tensor) or V.dtype != torch.float64 or not V.is_cuda:
+        raise TypeError(f"{name} must be a float64 CUDA (HIP) tensor")
+    if V.dim() != 2 or tuple(V.shape) != (m, n) or V.stride(1) != 1 or V.stride(0) < n:
+        raise ValueError(f"{name} must be a row-major {m} x {n} matrix with unit column stride")
+
+
+class Plan:
+    """A factorization plan for m x n inputs with CountSketch size s1, Gaussian size s2, seed."""
+
+    def __init__(self, m, n, s1, s2, seed, device=None, stream=None):
+        self.m, self.n, self.s1, self.s2, self.seed = int(m), int(n), int(s1), int(s2), int(seed)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        nbytes = workspace_bytes(self.m, self.n, self.s1, self.s2)
+        if nbytes == 0:
+            raise RcqrError(E_UNSUPPORTED if 0 < n and n > MAX_N else E_INVALID, "rcqr_workspace_bytes")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        handle = ctypes.c_void_p()
+        _check(lib().rcqr_plan(ctypes.byref(handle), self.m, self.n, self.s1, self.s2, self.seed, 0,
+                               ctypes.c_void_p(self.workspace.data_ptr()), nbytes, _stream_ptr(self.stream)), "rcqr_plan")
+        self._h = handle
+
+    # -- lifecycle ---------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rcqr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- factorizations ------------------------------------------------------------------
+    def _outputs(self, V, Q, R):
+        _check_matrix(V, self.m, self.n, "V")
+        if Q is None:
+            Q = torch.empty((self.m, self.n), dtype=torch.float64, device=V.device)
+        if R is None:
+            R = torch.empty((self.n, self.n), dtype=torch.float64, device=V.device)
+        _check_matrix(Q, self.m, self.n, "Q")
+        _check_matrix(R, self.n, self.n, "R")
+        return Q, R
+
+    def factor(self, V, Q=None, R=None, check=True):
+        """Algorithm 3 on V; returns (Q, R).  With check=True waits and raises on RANK/CHOL."""
+        Q, R = self._outputs(V, Q, R)
+        _check(lib().rcqr_factor(self._h, ctypes.c_void_p(V.data_ptr()), V.stride(0), ctypes.c_void_p(Q.data_ptr()),
+                                 Q.stride(0), ctypes.c_void_p(R.data_ptr()), R.stride(0)), "rcqr_factor")
+        if check:
+            self.raise_on_failure("rcqr_factor")
+        return Q, R
+
+    def cholqr2(self, V, Q=None, R=None, check=True):
+        """Algorithm 4 (cholQR2) on V with this plan's workspace; returns (Q, R)."""
+        Q, R = self._outputs(V, Q, R)
+        _check(lib().rcqr_cholqr2(self._h, ctypes.c_void_p(V.data_ptr()), V.stride(0), ctypes.c_void_p(Q.data_ptr()),
+                                  Q.stride(0), ctypes.c_void_p(R.data_ptr()), R.stride(0)), "rcqr_cholqr2")
+        if check:
+            self.raise_on_failure("rcqr_cholqr2")
+        return Q, R
+
+    def info(self):
+        st, col = _c_i32(), _c_i32()
+        _check(lib().rcqr_info(self._h, ctypes.byref(st), ctypes.byref(col)), "rcqr_info")
+        return st.value, col.value
+
+    def raise_on_failure(self, what):
+        st, col = self.info()
+        if st != OK:
+            raise RcqrError(st, what, col)
+
+    # -- timing ----------------------------------------------------------------------------
+    def set_timing(self, steps=1):
+        """Record per-phase HIP events for the next `steps` factor calls (0 turns it off)."""
+        _check(lib().rcqr_set_timing(self._h, int(steps)), "rcqr_set_timing")
+
+    def phase_times(self):
+        """Mean per-phase milliseconds over the factor calls recorded since the last read."""
+        arr = (ctypes.c_float * 16)()
+        cnt = _c_i32()
+        _check(lib().rcqr_phase_times(self._h, arr, 16, ctypes.byref(cnt)), "rcqr_phase_times")
+        return {lib().rcqr_phase_name(i).decode(): float(arr[i]) for i in range(cnt.value)}
+
+    # -- inspection --------------------------------------------------------------------------
+    def sketch_hash(self, row0, count):
+        b = torch.empty(count, dtype=torch.int32, device=self.device)
+        g = torch.empty(count, dtype=torch.int8, device=self.device)
+        _check(lib().rcqr_sketch_hash(self._h, row0, count, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(g.data_ptr())),
+               "rcqr_sketch_hash")
+        return b, g
+
+    def gaussian_block(self, j0, nj, k0, nk):
+        out = torch.empty((nj, nk), dtype=torch.float64, device=self.device)
+        _check(lib().rcqr_gaussian_block(self._h, j0, nj, k0, nk, ctypes.c_void_p(out.data_ptr())), "rcqr_gaussian_block")
+        return out
+
+    def intermediates(self):
+        f = lambda *s: torch.empty(s, dtype=torch.float64, device=self.device)  # noqa: E731
+        out = {"W1": f(self.s1, self.n), "W": f(self.s2, self.n), "R0": f(self.n, self.n), "G": f(self.n, self.n),
+               "R1": f(self.n, self.n)}
+        ptr = {k: ctypes.c_void_p(v.data_ptr()) for k, v in out.items()}
+        _check(lib().rcqr_intermediates(self._h, ptr["W1"], ptr["W"], ptr["R0"], ptr["G"], ptr["R1"]), "rcqr_intermediates")
+        return out
+
+    def q0_twice(self, V):
+        _check_matrix(V, self.m, self.n, "V")
+        a = torch.empty((self.m, self.n), dtype=torch.float64, device=V.device)
+        b = torch.empty_like(a)
+        _check(lib().rcqr_q0_twice(self._h, ctypes.c_void_p(V.data_ptr()), V.stride(0), ctypes.c_void_p(a.data_ptr()),
+                                   ctypes.c_void_p(b.data_ptr()), self.n), "rcqr_q0_twice")
+        return a, b
+
+
+def rand_cholqr(V, s1, s2, seed, check=True):
+    """One-shot Algorithm 3: returns (Q, R) for the CUDA float64 matrix V."""
+    m, n = V.shape
+    with Plan(m, n, s1, s2, seed, device=V.device) as p:
+        Q, R = p.factor(V, check=check)
+        torch.cuda.current_stream(V.device).synchronize()
+        return Q, R
+
+
+def cholqr2(V, check=True):
+    """One-shot Algorithm 4 (cholQR2) on the GPU; returns (Q, R)."""
+    m, n = V.shape
+    with Plan(m, n, max(n, 16), n, 0, device=V.device) as p:
+        Q, R = p.cholqr2(V, check=check)
+        torch.cuda.current_stream(V.device).synchronize()
+        return Q, R

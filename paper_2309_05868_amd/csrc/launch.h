@@ -1,0 +1,67 @@
+// Host-callable launchers of the rcqr kernels (one per kernel family).  Every launcher only
+// enqueues work on `s` and returns the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rcqr {
+
+// --- sketch.hip --------------------------------------------------------------------------
+hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t s);
+hipError_t launch_fill_f64(double* p, int64_t count, double value, hipStream_t s);
+// codes[i] = (h(i) << 1) | signbit(i) for i < m; counts[h(i)] += 1 when counts != nullptr.
+hipError_t launch_hash_codes(int64_t m, int64_t s1, uint64_t seed, uint32_t* codes, uint32_t* counts, hipStream_t s);
+// offsets[0..s1] = exclusive scan of counts; cursor[b] = offsets[b].
+hipError_t launch_bucket_scan(const uint32_t* counts, int64_t s1, uint32_t* offsets, uint32_t* cursor, hipStream_t s);
+// entries[cursor[h(i)]++] = (i << 1) | signbit(i).
+hipError_t launch_bucket_scatter(int64_t m, const uint32_t* codes, uint32_t* cursor, uint32_t* entries, hipStream_t s);
+// W1[b, :] = sum over the bucket's rows (ascending row order) of sign * V[row, :].
+hipError_t launch_bucket_gather(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, const uint32_t* offsets,
+                                const uint32_t* entries, double* W1, hipStream_t s);
+// Small-s1 CountSketch: per-wave LDS copies of W1; writes one partial W1 per workgroup.
+int countsketch_lds_parts(int64_t m);
+bool countsketch_lds_fits(int64_t s1, int n);
+hipError_t launch_countsketch_lds(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, uint64_t seed,
+                                  double* parts, int nparts, hipStream_t s);
+// Wpart[kc] = S2[:, kc-th chunk of KC columns] * W1[chunk, :], S2 generated on the fly.
+hipError_t launch_gauss_gemm(const double* W1, int n, int64_t s1, int64_t s2, uint64_t seed, double scale, int64_t kc_len,
+                             int64_t nkc, double* wpart, hipStream_t s);
+// out[i] = sum_{p = 0..nparts-1} parts[p * stride + i] in increasing p.
+hipError_t launch_reduce_parts(const double* parts, int64_t nparts, int64_t stride, int64_t len, double* out,
+                               hipStream_t s);
+hipError_t launch_hash_debug(int64_t row0, int64_t count, int64_t s1, uint64_t seed, int32_t* bucket, int8_t* sign,
+                             hipStream_t s);
+hipError_t launch_gaussian_block(int64_t j0, int64_t nj, int64_t k0, int64_t nk, uint64_t seed, double scale,
+                                 double* out, hipStream_t s);
+
+// --- smalldense.hip ------------------------------------------------------------------------
+// R (n x n, row-major, ld n) = R factor of the p x n block `in` (ld ldin, p <= 256) by
+// Householder reflections; rows of R beyond min(p, n) are zero.  One workgroup per block:
+// block b reads rows [b*rows_per_block, ...) and writes out + b*n*n.
+hipError_t launch_qr_blocks(const double* in, int64_t ldin, int64_t p_total, int64_t rows_per_block, int n, double* out,
+                            int nblocks, hipStream_t s);
+// Sign-normalise the Householder R (rows scaled so the diagonal is positive), check its
+// diagonal (status RANK on zero / non-finite), write R0 (n x n) and its packed padded form.
+hipError_t launch_finalize_r0(const double* rin, int n, int np, int32_t* info, double* r0, double* r0pk, hipStream_t s);
+// Cholesky of the Gram matrix held as compact upper 16x16 blocks; writes G (n x n, upper,
+// lower zero), R1 and its packed padded form, and R = R1 * Rprev into the caller's R
+// (ld ldr).  A non-positive pivot sets status CHOL.
+hipError_t launch_cholesky(const double* gcompact, int n, int np, const double* rprev, int32_t* info, double* g_out,
+                           double* r1, double* r1pk, double* r_out, int64_t ldr, hipStream_t s);
+// Identity (n x n) into r0 and its packed padded form into r0pk.
+hipError_t launch_identity_factor(int n, int np, double* r0, double* r0pk, hipStream_t s);
+
+// --- stream.hip ------------------------------------------------------------------------------
+constexpr int kGramBlocks = 256;     // workgroups of the Gram pass (fixed: fixes the sum order)
+constexpr int kGramThreads = 512;
+int gram_compact_len(int np);        // doubles per compact Gram partial
+int packed_len(int np);              // doubles of a packed np x np triangular factor
+// Packed factor format (R padded to np columns with an identity block): the upper triangle
+// row by row, the reciprocal of each diagonal entry in place of the entry.
+hipError_t launch_trsm_gram(int np, const double* V, int64_t m, int n, int64_t ldv, const double* r0pk, const int32_t* info,
+                            double* gpart, double* q0, int64_t ldq, hipStream_t s);
+hipError_t launch_final(int np, bool apply_r1, const double* V, int64_t m, int n, int64_t ldv, const double* r0pk,
+                        const double* r1pk, const int32_t* info, double* Q, int64_t ldq, hipStream_t s);
+
+}  // namespace rcqr

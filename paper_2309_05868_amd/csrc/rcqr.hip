@@ -1,0 +1,421 @@
+// Host side of the rcqr C ABI: argument checks, workspace layout, and the order of the kernel
+// launches of Algorithm 3 (rand_cholQR) and Algorithm 4 (cholQR2) on the plan's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "../../include/rcqr.h"
+#include "launch.h"
+
+using namespace rcqr;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kQrRows = 256;     // rows one Householder workgroup factors
+constexpr int kPhases = 6;
+constexpr int64_t kMaxRows = (int64_t)1 << 31;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int padded_cols(int64_t n) {
+  int p = 16;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+struct Layout {
+  size_t info, w1, csparts, codes, counts, offsets, cursor, entries, wpart, w, qra, qrb, r0, r0pk, gpart, gc, g, r1, r1pk,
+      ra, rapk, rtmp, total;
+};
+
+struct Shape {
+  int64_t m, n, s1, s2;
+  int np;
+  bool lds_cs;
+  int cs_parts;
+  int64_t kc_len, nkc;
+  int64_t qr_blocks0;
+};
+
+Shape make_shape(int64_t m, int64_t n, int64_t s1, int64_t s2) {
+  Shape sh{};
+  sh.m = m;
+  sh.n = n;
+  sh.s1 = s1;
+  sh.s2 = s2;
+  sh.np = padded_cols(n);
+  sh.lds_cs = countsketch_lds_fits(s1, (int)n);
+  sh.cs_parts = sh.lds_cs ? countsketch_lds_parts(m) : 0;
+  // Gaussian GEMM split over s1: about 512 workgroups, partials capped at 16 MiB
+  const int64_t nrb = (s2 + 63) / 64;
+  int64_t nkc = 512 / nrb;
+  const int64_t cap = (int64_t)(16u << 20) / (s2 * n * 8);
+  if (nkc > cap) nkc = cap;
+  if (nkc < 1) nkc = 1;
+  const int64_t maxk = (s1 + 15) / 16;
+  if (nkc > maxk) nkc = maxk;
+  int64_t kc = (s1 + nkc - 1) / nkc;
+  kc = (kc + 15) / 16 * 16;
+  sh.kc_len = kc;
+  sh.nkc = (s1 + kc - 1) / kc;
+  sh.qr_blocks0 = (s2 + kQrRows - 1) / kQrRows;
+  return sh;
+}
+
+Layout make_layout(const Shape& sh) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + (bytes ? bytes : 1));
+    return at;
+  };
+  const size_t n = (size_t)sh.n, np = (size_t)sh.np;
+  L.info = take(16 * sizeof(int32_t));
+  L.w1 = take((size_t)sh.s1 * n * 8);
+  L.csparts = take(sh.lds_cs ? (size_t)sh.cs_parts * sh.s1 * n * 8 : 0);
+  const size_t mm = sh.lds_cs ? 0 : (size_t)sh.m;
+  const size_t ss = sh.lds_cs ? 0 : (size_t)sh.s1;
+  L.codes = take(mm * 4);
+  L.counts = take(ss * 4);
+  L.offsets = take(sh.lds_cs ? 0 : (ss + 1) * 4);
+  L.cursor = take(ss * 4);
+  L.entries = take(mm * 4);
+  L.wpart = take((size_t)sh.nkc * sh.s2 * n * 8);
+  L.w = take((size_t)sh.s2 * n * 8);
+  L.qra = take((size_t)sh.qr_blocks0 * n * n * 8);
+  L.qrb = take((size_t)sh.qr_blocks0 * n * n * 8);
+  const size_t pk = (size_t)packed_len((int)np) * 8;
+  L.r0 = take(n * n * 8);
+  L.r0pk = take(pk);
+  L.gpart = take((size_t)kGramBlocks * gram_compact_len((int)np) * 8);
+  L.gc = take((size_t)gram_compact_len((int)np) * 8);
+  L.g = take(n * n * 8);
+  L.r1 = take(n * n * 8);
+  L.r1pk = take(pk);
+  L.ra = take(n * n * 8);
+  L.rapk = take(pk);
+  L.rtmp = take(n * n * 8);
+  L.total = off;
+  return L;
+}
+
+rcqr_status_t check_shape(int64_t m, int64_t n, int64_t s1, int64_t s2) {
+  if (n < 1 || m < n || s2 < n || s1 < s2) return RCQR_E_INVALID;
+  if (m >= kMaxRows || s1 >= kMaxRows) return RCQR_E_INVALID;
+  if (n > 64) return RCQR_E_UNSUPPORTED;
+  return RCQR_OK;
+}
+
+const char* const kPhaseNames[kPhases] = {"countsketch", "gaussian", "householder", "trsm_gram", "cholesky", "final"};
+
+}  // namespace
+
+struct rcqr_plan_s {
+  Shape sh;
+  Layout L;
+  uint64_t seed;
+  uint32_t flags;
+  hipStream_t stream;
+  char* ws;
+  // per-phase timing: a ring of `cap` steps, kPhases + 1 events each
+  int cap;
+  int recorded;
+  hipEvent_t* ev;
+
+  template <class T>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(ws + off);
+  }
+};
+
+#define RCQR_TRY(expr)                       \
+  do {                                       \
+    if ((expr) != hipSuccess) return RCQR_E_HIP; \
+  } while (0)
+
+static rcqr_status_t mark(rcqr_plan_t p, int i) {
+  if (p->cap > 0) {
+    const int slot = p->recorded % p->cap;
+    RCQR_TRY(hipEventRecord(p->ev[slot * (kPhases + 1) + i], p->stream));
+  }
+  return RCQR_OK;
+}
+
+static void free_events(rcqr_plan_t p) {
+  if (p->ev) {
+    for (int i = 0; i < p->cap * (kPhases + 1); ++i)
+      if (p->ev[i]) (void)hipEventDestroy(p->ev[i]);
+    delete[] p->ev;
+  }
+  p->ev = nullptr;
+  p->cap = 0;
+  p->recorded = 0;
+}
+
+// R0 = Householder R of W (s2 x n): TSQR over 256-row blocks, then sign normalisation.
+static rcqr_status_t run_householder(rcqr_plan_t p) {
+  const Shape& sh = p->sh;
+  const int n = (int)sh.n;
+  hipStream_t s = p->stream;
+  const double* in = p->at<double>(p->L.w);
+  int64_t rows = sh.s2, rpb = kQrRows;
+  double* bufs[2] = {p->at<double>(p->L.qra), p->at<double>(p->L.qrb)};
+  int which = 0;
+  for (;;) {
+    const int64_t nblocks = (rows + rpb - 1) / rpb;
+    RCQR_TRY(launch_qr_blocks(in, n, rows, rpb, n, bufs[which], (int)nblocks, s));
+    in = bufs[which];
+    which ^= 1;
+    if (nblocks == 1) break;
+    rows = nblocks * n;
+    rpb = (kQrRows / n) * n;
+  }
+  RCQR_TRY(launch_finalize_r0(in, n, sh.np, p->at<int32_t>(p->L.info), p->at<double>(p->L.r0), p->at<double>(p->L.r0pk), s));
+  return RCQR_OK;
+}
+
+// G = (V Rp^{-1})^T (V Rp^{-1}) into the compact buffer.
+static rcqr_status_t run_gram(rcqr_plan_t p, const double* V, int64_t ldv, const double* rpk) {
+  const Shape& sh = p->sh;
+  const int len = gram_compact_len(sh.np);
+  RCQR_TRY(launch_trsm_gram(sh.np, V, sh.m, (int)sh.n, ldv, rpk, p->at<int32_t>(p->L.info), p->at<double>(p->L.gpart), nullptr,
+                            0, p->stream));
+  RCQR_TRY(launch_reduce_parts(p->at<double>(p->L.gpart), kGramBlocks, len, len, p->at<double>(p->L.gc), p->stream));
+  return RCQR_OK;
+}
+
+extern "C" {
+
+size_t rcqr_workspace_bytes(int64_t m, int64_t n, int64_t s1, int64_t s2, uint32_t flags) {
+  (void)flags;
+  if (check_shape(m, n, s1, s2) != RCQR_OK) return 0;
+  return make_layout(make_shape(m, n, s1, s2)).total;
+}
+
+rcqr_status_t rcqr_plan(rcqr_plan_t* plan, int64_t m, int64_t n, int64_t s1, int64_t s2, uint64_t seed, uint32_t flags,
+                        void* d_workspace, size_t workspace_bytes, void* stream) {
+  if (plan == nullptr) return RCQR_E_INVALID;
+  *plan = nullptr;
+  const rcqr_status_t st = check_shape(m, n, s1, s2);
+  if (st != RCQR_OK) return st;
+  if (flags != 0) return RCQR_E_INVALID;
+  const Shape sh = make_shape(m, n, s1, s2);
+  const Layout L = make_layout(sh);
+  if (d_workspace == nullptr || workspace_bytes < L.total || (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) != 0)
+    return RCQR_E_INVALID;
+  rcqr_plan_s* p = new (std::nothrow) rcqr_plan_s();
+  if (p == nullptr) return RCQR_E_NOMEM;
+  p->sh = sh;
+  p->L = L;
+  p->seed = seed;
+  p->flags = flags;
+  p->stream = reinterpret_cast<hipStream_t>(stream);
+  p->ws = reinterpret_cast<char*>(d_workspace);
+  p->cap = 0;
+  p->recorded = 0;
+  p->ev = nullptr;
+  *plan = p;
+  return RCQR_OK;
+}
+
+rcqr_status_t rcqr_destroy(rcqr_plan_t p) {
+  if (p == nullptr) return RCQR_E_INVALID;
+  free_events(p);
+  delete p;
+  return RCQR_OK;
+}
+
+rcqr_status_t rcqr_set_timing(rcqr_plan_t p, int32_t steps) {
+  if (p == nullptr || steps < 0 || steps > 4096) return RCQR_E_INVALID;
+  free_events(p);
+  if (steps == 0) return RCQR_OK;
+  p->ev = new (std::nothrow) hipEvent_t[(size_t)steps * (kPhases + 1)]();
+  if (p->ev == nullptr) return RCQR_E_NOMEM;
+  p->cap = steps;
+  for (int i = 0; i < steps * (kPhases + 1); ++i) {
+    if (hipEventCreate(&p->ev[i]) != hipSuccess) {
+      free_events(p);
+      return RCQR_E_HIP;
+    }
+  }
+  return RCQR_OK;
+}
+
+rcqr_status_t rcqr_phase_times(rcqr_plan_t p, float* ms, int32_t max, int32_t* count) {
+  if (p == nullptr || count == nullptr || (ms == nullptr && max > 0)) return RCQR_E_INVALID;
+  *count = 0;
+  if (p->cap == 0 || p->recorded == 0) return RCQR_E_INVALID;
+  RCQR_TRY(hipStreamSynchronize(p->stream));
+  const int steps = p->recorded < p->cap ? p->recorded : p->cap;
+  const int k = max < kPhases ? max : kPhases;
+  for (int i = 0; i < k; ++i) {
+    double sum = 0.0;
+    for (int st = 0; st < steps; ++st) {
+      float t = 0.f;
+      RCQR_TRY(hipEventElapsedTime(&t, p->ev[st * (kPhases + 1) + i], p->ev[st * (kPhases + 1) + i + 1]));
+      sum += t;
+    }
+    ms[i] = (float)(sum / steps);
+  }
+  *count = kPhases;
+  p->recorded = 0;
+  return RCQR_OK;
+}
+
+const char* rcqr_phase_name(int32_t phase) { return (phase >= 0 && phase < kPhases) ? kPhaseNames[phase] : "?"; }
+
+const char* rcqr_status_string(int32_t status) {
+  switch (status) {
+    case RCQR_OK: return "ok";
+    case RCQR_E_INVALID: return "invalid argument";
+    case RCQR_E_UNSUPPORTED: return "unsupported shape";
+    case RCQR_E_NOMEM: return "out of host memory";
+    case RCQR_E_HIP: return "HIP runtime error";
+    case RCQR_E_RANK: return "sketch R0 has a zero or non-finite diagonal entry";
+    case RCQR_E_CHOL: return "Cholesky of the Gram matrix met a non-positive pivot";
+    default: return "unknown status";
+  }
+}
+
+static rcqr_status_t check_io(rcqr_plan_t p, const double* V, int64_t ldv, double* Q, int64_t ldq, double* R, int64_t ldr) {
+  if (p == nullptr || V == nullptr || Q == nullptr || R == nullptr) return RCQR_E_INVALID;
+  if (ldv < p->sh.n || ldq < p->sh.n || ldr < p->sh.n) return RCQR_E_INVALID;
+  if ((const void*)Q == (const void*)V && ldq != ldv) return RCQR_E_INVALID;
+  return RCQR_OK;
+}
+
+rcqr_status_t rcqr_factor(rcqr_plan_t p, const double* V, int64_t ldv, double* Q, int64_t ldq, double* R, int64_t ldr) {
+  const rcqr_status_t st = check_io(p, V, ldv, Q, ldq, R, ldr);
+  if (st != RCQR_OK) return st;
+  const Shape& sh = p->sh;
+  const Layout& L = p->L;
+  const int n = (int)sh.n;
+  hipStream_t s = p->stream;
+  int32_t* info = p->at<int32_t>(L.info);
+  double* W1 = p->at<double>(L.w1);
+
+  RCQR_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(info), 16, 0u, s));
+  if (mark(p, 0) != RCQR_OK) return RCQR_E_HIP;
+  // Algorithm 1, step 1: W1 = S1 V
+  if (sh.lds_cs) {
+    double* parts = p->at<double>(L.csparts);
+    RCQR_TRY(launch_countsketch_lds(V, ldv, sh.m, n, sh.s1, p->seed, parts, sh.cs_parts, s));
+    RCQR_TRY(launch_reduce_parts(parts, sh.cs_parts, sh.s1 * sh.n, sh.s1 * sh.n, W1, s));
+  } else {
+    uint32_t* counts = p->at<uint32_t>(L.counts);
+    uint32_t* offsets = p->at<uint32_t>(L.offsets);
+    uint32_t* cursor = p->at<uint32_t>(L.cursor);
+    uint32_t* codes = p->at<uint32_t>(L.codes);
+    uint32_t* entries = p->at<uint32_t>(L.entries);
+    RCQR_TRY(launch_fill_u32(counts, sh.s1, 0u, s));
+    RCQR_TRY(launch_hash_codes(sh.m, sh.s1, p->seed, codes, counts, s));
+    RCQR_TRY(launch_bucket_scan(counts, sh.s1, offsets, cursor, s));
+    RCQR_TRY(launch_bucket_scatter(sh.m, codes, cursor, entries, s));
+    RCQR_TRY(launch_bucket_gather(V, ldv, sh.m, n, sh.s1, offsets, entries, W1, s));
+  }
+  if (mark(p, 1) != RCQR_OK) return RCQR_E_HIP;
+  // Algorithm 1, step 1: W = S2 W1
+  {
+    const double scale = 1.0 / std::sqrt((double)sh.s2);
+    double* wpart = p->at<double>(L.wpart);
+    RCQR_TRY(launch_gauss_gemm(W1, n, sh.s1, sh.s2, p->seed, scale, sh.kc_len, sh.nkc, wpart, s));
+    RCQR_TRY(launch_reduce_parts(wpart, sh.nkc, sh.s2 * sh.n, sh.s2 * sh.n, p->at<double>(L.w), s));
+  }
+  if (mark(p, 2) != RCQR_OK) return RCQR_E_HIP;
+  // Algorithm 1, step 2: R0 = hhqr(W)
+  if (run_householder(p) != RCQR_OK) return RCQR_E_HIP;
+  if (mark(p, 3) != RCQR_OK) return RCQR_E_HIP;
+  // Algorithm 1, step 3 + Algorithm 2, step 1: Q0 = V R0^{-1}, G = Q0^T Q0
+  if (run_gram(p, V, ldv, p->at<double>(L.r0pk)) != RCQR_OK) return RCQR_E_HIP;
+  if (mark(p, 4) != RCQR_OK) return RCQR_E_HIP;
+  // Algorithm 2, step 2 and Algorithm 3, step 3: R1 = chol(G), R = R1 R0
+  RCQR_TRY(launch_cholesky(p->at<double>(L.gc), n, sh.np, p->at<double>(L.r0), info, p->at<double>(L.g), p->at<double>(L.r1),
+                           p->at<double>(L.r1pk), R, ldr, s));
+  if (mark(p, 5) != RCQR_OK) return RCQR_E_HIP;
+  // Algorithm 2, step 3 on Q0: Q = Q0 R1^{-1}
+  RCQR_TRY(launch_final(sh.np, true, V, sh.m, n, ldv, p->at<double>(L.r0pk), p->at<double>(L.r1pk), info, Q, ldq, s));
+  if (mark(p, 6) != RCQR_OK) return RCQR_E_HIP;
+  if (p->cap > 0) ++p->recorded;
+  return RCQR_OK;
+}
+
+rcqr_status_t rcqr_cholqr2(rcqr_plan_t p, const double* V, int64_t ldv, double* Q, int64_t ldq, double* R, int64_t ldr) {
+  const rcqr_status_t st = check_io(p, V, ldv, Q, ldq, R, ldr);
+  if (st != RCQR_OK) return st;
+  const Shape& sh = p->sh;
+  const Layout& L = p->L;
+  const int n = (int)sh.n;
+  hipStream_t s = p->stream;
+  int32_t* info = p->at<int32_t>(L.info);
+  RCQR_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(info), 16, 0u, s));
+  // first cholQR: G = V^T V (R0 := I), Ra = chol(G)
+  RCQR_TRY(launch_identity_factor(n, sh.np, p->at<double>(L.r0), p->at<double>(L.r0pk), s));
+  if (run_gram(p, V, ldv, p->at<double>(L.r0pk)) != RCQR_OK) return RCQR_E_HIP;
+  RCQR_TRY(launch_cholesky(p->at<double>(L.gc), n, sh.np, p->at<double>(L.r0), info, p->at<double>(L.g), p->at<double>(L.ra),
+                           p->at<double>(L.rapk), p->at<double>(L.rtmp), n, s));
+  // second cholQR on Q0 = V Ra^{-1}: Rb = chol(Q0^T Q0), R = Rb Ra
+  if (run_gram(p, V, ldv, p->at<double>(L.rapk)) != RCQR_OK) return RCQR_E_HIP;
+  RCQR_TRY(launch_cholesky(p->at<double>(L.gc), n, sh.np, p->at<double>(L.rtmp), info, p->at<double>(L.g), p->at<double>(L.r1),
+                           p->at<double>(L.r1pk), R, ldr, s));
+  RCQR_TRY(launch_final(sh.np, true, V, sh.m, n, ldv, p->at<double>(L.rapk), p->at<double>(L.r1pk), info, Q, ldq, s));
+  return RCQR_OK;
+}
+
+rcqr_status_t rcqr_info(rcqr_plan_t p, int32_t* status, int32_t* column) {
+  if (p == nullptr || status == nullptr || column == nullptr) return RCQR_E_INVALID;
+  int32_t h[2] = {0, 0};
+  RCQR_TRY(hipMemcpyAsync(h, p->at<int32_t>(p->L.info), sizeof(h), hipMemcpyDeviceToHost, p->stream));
+  RCQR_TRY(hipStreamSynchronize(p->stream));
+  *status = h[0];
+  *column = h[1];
+  return RCQR_OK;
+}
+
+rcqr_status_t rcqr_sketch_hash(rcqr_plan_t p, int64_t row0, int64_t count, int32_t* d_bucket, int8_t* d_sign) {
+  if (p == nullptr || row0 < 0 || count < 0 || row0 + count > kMaxRows || (count > 0 && (!d_bucket || !d_sign)))
+    return RCQR_E_INVALID;
+  RCQR_TRY(launch_hash_debug(row0, count, p->sh.s1, p->seed, d_bucket, d_sign, p->stream));
+  return RCQR_OK;
+}
+
+rcqr_status_t rcqr_gaussian_block(rcqr_plan_t p, int64_t j0, int64_t nj, int64_t k0, int64_t nk, double* d_out) {
+  if (p == nullptr || j0 < 0 || nj < 0 || k0 < 0 || nk < 0 || (nj * nk > 0 && d_out == nullptr)) return RCQR_E_INVALID;
+  const double scale = 1.0 / std::sqrt((double)p->sh.s2);
+  RCQR_TRY(launch_gaussian_block(j0, nj, k0, nk, p->seed, scale, d_out, p->stream));
+  return RCQR_OK;
+}
+
+rcqr_status_t rcqr_intermediates(rcqr_plan_t p, double* d_W1, double* d_W, double* d_R0, double* d_G, double* d_R1) {
+  if (p == nullptr) return RCQR_E_INVALID;
+  const Shape& sh = p->sh;
+  const size_t nn = (size_t)sh.n * sh.n * 8;
+  struct {
+    double* dst;
+    size_t off, bytes;
+  } c[5] = {{d_W1, p->L.w1, (size_t)sh.s1 * sh.n * 8},
+            {d_W, p->L.w, (size_t)sh.s2 * sh.n * 8},
+            {d_R0, p->L.r0, nn},
+            {d_G, p->L.g, nn},
+            {d_R1, p->L.r1, nn}};
+  for (auto& e : c)
+    if (e.dst) RCQR_TRY(hipMemcpyAsync(e.dst, p->ws + e.off, e.bytes, hipMemcpyDeviceToDevice, p->stream));
+  return RCQR_OK;
+}
+
+rcqr_status_t rcqr_q0_twice(rcqr_plan_t p, const double* V, int64_t ldv, double* Q0a, double* Q0b, int64_t ldq) {
+  if (p == nullptr || V == nullptr || Q0a == nullptr || Q0b == nullptr || ldv < p->sh.n || ldq < p->sh.n) return RCQR_E_INVALID;
+  const Shape& sh = p->sh;
+  const Layout& L = p->L;
+  RCQR_TRY(launch_trsm_gram(sh.np, V, sh.m, (int)sh.n, ldv, p->at<double>(L.r0pk), p->at<int32_t>(L.info), p->at<double>(L.gpart),
+                            Q0a, ldq, p->stream));
+  RCQR_TRY(launch_final(sh.np, false, V, sh.m, (int)sh.n, ldv, p->at<double>(L.r0pk), p->at<double>(L.r1pk), p->at<int32_t>(L.info),
+                        Q0b, ldq, p->stream));
+  return RCQR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,539 @@
+// Sketch kernels: CountSketch W1 = S1 V and Gaussian sketch W = S2 W1 (Algorithm 1, step 1).
+//
+// The CountSketch has one +-1 per column of S1 (Section 3), so W1 = S1 V adds or subtracts
+// rows of V into s1 buckets (Section 4.2).  Two strategies, both deterministic:
+//   * small s1*n (<= 4096 entries): every wave keeps a private copy of W1 in LDS and streams
+//     contiguous rows of V; rows of one batch that share a bucket are first combined by the
+//     lowest such lane, in row order; the copies are summed in fixed order.
+//   * otherwise: a bucket index (CSR of S1) is built per call -- hash codes, bucket counts,
+//     exclusive scan, scatter of (row, sign) -- and one wave per bucket gathers its rows.  The
+//     wave sorts its bucket's entries by row before summing, so the sum order is ascending
+//     row order whatever order the scatter's atomics produced.
+// The Gaussian sketch S2 = G / sqrt(s2) (Section 3) is never stored: each GEMM workgroup
+// regenerates its 64 x 16 tiles of S2 from Philox counters in LDS.
+#include "device_common.h"
+#include "launch.h"
+
+namespace rcqr {
+
+// ------------------------------------------------------------------------------------------
+// fills
+// ------------------------------------------------------------------------------------------
+__global__ void fill_u32_kernel(uint32_t* p, int64_t count, uint32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void fill_f64_kernel(double* p, int64_t count, double v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+static int grid_for(int64_t count, int threads, int cap = 4096) {
+  int64_t g = (count + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(count, 256)), dim3(256), 0, s, p, count, value);
+  return hipGetLastError();
+}
+hipError_t launch_fill_f64(double* p, int64_t count, double value, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_f64_kernel, dim3(grid_for(count, 256)), dim3(256), 0, s, p, count, value);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// CountSketch hash: one Philox block serves rows 4q .. 4q+3.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void hash_codes_kernel(int64_t m, uint64_t s1, uint64_t seed, uint32_t* __restrict__ codes,
+                                                         uint32_t* __restrict__ counts) {
+  const int64_t nq = (m + 3) / 4;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
+    const Block4 y = philox4x64_10((uint64_t)q, 0, 0, kTagCountSketch, seed, 0);
+    const uint32_t c0 = countsketch_code(y.y0, s1), c1 = countsketch_code(y.y1, s1);
+    const uint32_t c2 = countsketch_code(y.y2, s1), c3 = countsketch_code(y.y3, s1);
+    const int64_t r = 4 * q;
+    if (r + 3 < m) {
+      *reinterpret_cast<uint4*>(codes + r) = make_uint4(c0, c1, c2, c3);
+    } else {
+      codes[r] = c0;
+      if (r + 1 < m) codes[r + 1] = c1;
+      if (r + 2 < m) codes[r + 2] = c2;
+    }
+    if (counts) {
+      atomicAdd(counts + (c0 >> 1), 1u);
+      if (r + 1 < m) atomicAdd(counts + (c1 >> 1), 1u);
+      if (r + 2 < m) atomicAdd(counts + (c2 >> 1), 1u);
+      if (r + 3 < m) atomicAdd(counts + (c3 >> 1), 1u);
+    }
+  }
+}
+
+hipError_t launch_hash_codes(int64_t m, int64_t s1, uint64_t seed, uint32_t* codes, uint32_t* counts, hipStream_t s) {
+  const int64_t nq = (m + 3) / 4;
+  if (nq <= 0) return hipSuccess;
+  hipLaunchKernelGGL(hash_codes_kernel, dim3(grid_for(nq, 256, 8192)), dim3(256), 0, s, m, (uint64_t)s1, seed, codes, counts);
+  return hipGetLastError();
+}
+
+// Debug: bucket and sign per row.
+__global__ void hash_debug_kernel(int64_t row0, int64_t count, uint64_t s1, uint64_t seed, int32_t* bucket, int8_t* sign) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t row = (uint64_t)(row0 + i);
+    const Block4 y = philox4x64_10(row >> 2, 0, 0, kTagCountSketch, seed, 0);
+    const uint32_t code = countsketch_code(block_word(y, (int)(row & 3)), s1);
+    bucket[i] = (int32_t)(code >> 1);
+    sign[i] = (code & 1) ? (int8_t)-1 : (int8_t)1;
+  }
+}
+
+hipError_t launch_hash_debug(int64_t row0, int64_t count, int64_t s1, uint64_t seed, int32_t* bucket, int8_t* sign,
+                             hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(hash_debug_kernel, dim3(grid_for(count, 256)), dim3(256), 0, s, row0, count, (uint64_t)s1, seed, bucket, sign);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Bucket index: exclusive scan (one workgroup) and scatter.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void bucket_scan_kernel(const uint32_t* __restrict__ counts, int64_t s1,
+                                                           uint32_t* __restrict__ offsets, uint32_t* __restrict__ cursor) {
+  __shared__ uint32_t part[1024];
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < s1; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    const uint32_t v = i < s1 ? counts[i] : 0u;
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {  // Hillis-Steele inclusive scan
+      const uint32_t add = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+      __syncthreads();
+      part[threadIdx.x] += add;
+      __syncthreads();
+    }
+    const uint32_t incl = part[threadIdx.x] + carry;
+    if (i < s1) {
+      offsets[i] = incl - v;
+      cursor[i] = incl - v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 1023) carry = incl;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) offsets[s1] = carry;
+}
+
+hipError_t launch_bucket_scan(const uint32_t* counts, int64_t s1, uint32_t* offsets, uint32_t* cursor, hipStream_t s) {
+  hipLaunchKernelGGL(bucket_scan_kernel, dim3(1), dim3(1024), 0, s, counts, s1, offsets, cursor);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void bucket_scatter_kernel(int64_t m, const uint32_t* __restrict__ codes,
+                                                             uint32_t* __restrict__ cursor, uint32_t* __restrict__ entries) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t code = codes[i];
+    const uint32_t pos = atomicAdd(cursor + (code >> 1), 1u);
+    entries[pos] = ((uint32_t)i << 1) | (code & 1u);
+  }
+}
+
+hipError_t launch_bucket_scatter(int64_t m, const uint32_t* codes, uint32_t* cursor, uint32_t* entries, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(bucket_scatter_kernel, dim3(grid_for(m, 256, 8192)), dim3(256), 0, s, m, codes, cursor, entries);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Bucket gather: one wave per bucket.
+// ------------------------------------------------------------------------------------------
+constexpr int kSortCap = 2048;  // entries one wave sorts in LDS at a time
+constexpr int kGatherWaves = 4;
+
+// Bitonic sort of keys[0..N) (N a power of two) by one wave.
+__device__ void wave_bitonic_sort(uint32_t* keys, int N, int lane) {
+  for (int k = 2; k <= N; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = lane; i < N; i += kWave) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint32_t a = keys[i], b = keys[ixj];
+          const bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            keys[i] = b;
+            keys[ixj] = a;
+          }
+        }
+      }
+      wave_lds_sync();
+    }
+  }
+}
+
+// Accumulate sorted entries keys[0..cnt) into acc: lane group g takes entries g, g+G, ...
+template <int NPL>
+__device__ __forceinline__ void gather_rows(const uint32_t* keys, int cnt, const double* __restrict__ V, int64_t ldv, int n,
+                                            int lane, double (&acc)[NPL > 64 ? 2 : 1]) {
+  constexpr int G = NPL >= 64 ? 1 : 64 / NPL;
+  const int g = NPL >= 64 ? 0 : lane / NPL;
+  const int c = NPL >= 64 ? lane : lane % NPL;
+  int e = g;
+  // four rows in flight, added in entry order
+  for (; e + 3 * G < cnt; e += 4 * G) {
+    const uint32_t k0 = keys[e], k1 = keys[e + G], k2 = keys[e + 2 * G], k3 = keys[e + 3 * G];
+    if constexpr (NPL > 64) {
+      double v[4][2];
+      const uint32_t kk[4] = {k0, k1, k2, k3};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double* row = V + (int64_t)(kk[u] >> 1) * ldv;
+        v[u][0] = c < n ? row[c] : 0.0;
+        v[u][1] = c + 64 < n ? row[c + 64] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const bool neg = kk[u] & 1u;
+        acc[0] += neg ? -v[u][0] : v[u][0];
+        acc[1] += neg ? -v[u][1] : v[u][1];
+      }
+    } else {
+      const uint32_t kk[4] = {k0, k1, k2, k3};
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = c < n ? V[(int64_t)(kk[u] >> 1) * ldv + c] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[0] += (kk[u] & 1u) ? -v[u] : v[u];
+    }
+  }
+  for (; e < cnt; e += G) {
+    const uint32_t k = keys[e];
+    const double* row = V + (int64_t)(k >> 1) * ldv;
+    const bool neg = k & 1u;
+    const double v0 = c < n ? row[c] : 0.0;
+    acc[0] += neg ? -v0 : v0;
+    if constexpr (NPL > 64) {
+      const double v1 = c + 64 < n ? row[c + 64] : 0.0;
+      acc[1] += neg ? -v1 : v1;
+    }
+  }
+}
+
+template <int NPL>
+__global__ __launch_bounds__(256) void bucket_gather_kernel(const double* __restrict__ V, int64_t ldv, int64_t m, int n, int64_t s1,
+                                                            const uint32_t* __restrict__ offsets,
+                                                            const uint32_t* __restrict__ entries, double* __restrict__ W1) {
+  __shared__ uint32_t keys_all[kGatherWaves][kSortCap];
+  const int wave = threadIdx.x / kWave;
+  const int lane = lane_id();
+  const int64_t b = (int64_t)blockIdx.x * kGatherWaves + wave;
+  if (b >= s1) return;  // whole wave leaves; no workgroup barrier below
+  uint32_t* keys = keys_all[wave];
+  const uint32_t beg = offsets[b];
+  const int64_t L = (int64_t)offsets[b + 1] - beg;
+  double acc[NPL > 64 ? 2 : 1];
+  acc[0] = 0.0;
+  if constexpr (NPL > 64) acc[1] = 0.0;
+
+  if (L <= kSortCap) {
+    int N = 1;
+    while (N < L) N <<= 1;
+    for (int i = lane; i < N; i += kWave) keys[i] = i < L ? entries[beg + i] : 0xFFFFFFFFu;
+    wave_lds_sync();
+    wave_bitonic_sort(keys, N, lane);
+    gather_rows<NPL>(keys, (int)L, V, ldv, n, lane, acc);
+  } else {
+    // Windows of rows [lo, hi) small enough to sort; together they visit the bucket's
+    // entries in ascending row order.
+    int64_t lo = 0, remaining = L;
+    while (remaining > 0) {
+      int64_t span = (m - lo) * (kSortCap / 2) / remaining;
+      if (span < 1) span = 1;
+      int64_t hi, cnt;
+      for (;;) {
+        hi = lo + span < m ? lo + span : m;
+        cnt = 0;
+        for (int64_t i = lane; i < L; i += kWave) {
+          const int64_t row = entries[beg + i] >> 1;
+          cnt += (row >= lo && row < hi) ? 1 : 0;
+        }
+        for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, kWave);
+        if (cnt <= kSortCap) break;
+        span = span / 2 > 0 ? span / 2 : 1;
+      }
+      int base = 0;
+      for (int64_t i0 = 0; i0 < L; i0 += kWave) {
+        const int64_t i = i0 + lane;
+        uint32_t key = 0;
+        bool pred = false;
+        if (i < L) {
+          key = entries[beg + i];
+          const int64_t row = key >> 1;
+          pred = row >= lo && row < hi;
+        }
+        const uint64_t mask = __ballot(pred);
+        const int pos = base + __popcll(mask & ((1ull << lane) - 1ull));
+        if (pred) keys[pos] = key;
+        base += __popcll(mask);
+      }
+      int N = 1;
+      while (N < cnt) N <<= 1;
+      for (int i = (int)cnt + lane; i < N; i += kWave) keys[i] = 0xFFFFFFFFu;
+      wave_lds_sync();
+      wave_bitonic_sort(keys, N, lane);
+      gather_rows<NPL>(keys, (int)cnt, V, ldv, n, lane, acc);
+      wave_lds_sync();
+      remaining -= cnt;
+      lo = hi;
+    }
+  }
+  if constexpr (NPL < 64) {
+    for (int off = NPL; off < kWave; off <<= 1) acc[0] += shfl_xor_d(acc[0], off);
+    if (lane < NPL && lane < n) W1[b * n + lane] = acc[0];
+  } else {
+    if (lane < n) W1[b * n + lane] = acc[0];
+    if constexpr (NPL > 64) {
+      if (lane + 64 < n) W1[b * n + lane + 64] = acc[1];
+    }
+  }
+}
+
+hipError_t launch_bucket_gather(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, const uint32_t* offsets,
+                                const uint32_t* entries, double* W1, hipStream_t s) {
+  const dim3 grid((unsigned)((s1 + kGatherWaves - 1) / kGatherWaves)), block(256);
+  if (n <= 8)
+    hipLaunchKernelGGL(bucket_gather_kernel<8>, grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, W1);
+  else if (n <= 16)
+    hipLaunchKernelGGL(bucket_gather_kernel<16>, grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, W1);
+  else if (n <= 32)
+    hipLaunchKernelGGL(bucket_gather_kernel<32>, grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, W1);
+  else if (n <= 64)
+    hipLaunchKernelGGL(bucket_gather_kernel<64>, grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, W1);
+  else
+    hipLaunchKernelGGL(bucket_gather_kernel<128>, grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, W1);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Small-s1 CountSketch: per-wave LDS copies of W1 (s1 x NPL), contiguous row chunks.
+// ------------------------------------------------------------------------------------------
+constexpr int kCsLdsDoubles = 4096;  // s1 * NPL limit (4 waves x 32 KiB)
+constexpr int kCsParts = 512;         // workgroups (and partial copies of W1)
+constexpr int kCsChunk = 256;         // rows hashed at once by one wave
+
+int countsketch_lds_parts(int64_t m) {
+  int64_t p = (m + kCsChunk - 1) / kCsChunk;
+  if (p > kCsParts) p = kCsParts;
+  return p < 1 ? 1 : (int)p;
+}
+
+static int npl_of(int n) {
+  int p = 8;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+bool countsketch_lds_fits(int64_t s1, int n) { return n <= 64 && s1 * npl_of(n) <= kCsLdsDoubles; }
+
+template <int NPL>
+__global__ __launch_bounds__(256) void countsketch_lds_kernel(const double* __restrict__ V, int64_t ldv, int64_t m, int n, int64_t s1,
+                                                              uint64_t seed, double* __restrict__ parts) {
+  __shared__ double w1[4][kCsLdsDoubles];
+  __shared__ uint32_t codes[4][kCsChunk];
+  constexpr int RB = kWave / NPL;  // rows per batch
+  const int wave = threadIdx.x / kWave, lane = lane_id();
+  const int q = lane / NPL, c = lane % NPL;
+  double* mine = w1[wave];
+  for (int i = lane; i < s1 * NPL; i += kWave) mine[i] = 0.0;
+  // rows of this workgroup
+  const int64_t per = ((m + gridDim.x - 1) / gridDim.x + kCsChunk - 1) / kCsChunk * kCsChunk;
+  const int64_t r_beg = (int64_t)blockIdx.x * per;
+  const int64_t r_end = r_beg + per < m ? r_beg + per : m;
+  wave_lds_sync();
+  for (int64_t base = r_beg + (int64_t)wave * kCsChunk; base < r_end; base += 4 * kCsChunk) {
+    // hash the chunk: lane computes the Philox block of rows base + 4*lane .. +3 (base % 4 == 0)
+    {
+      const Block4 y = philox4x64_10((uint64_t)(base >> 2) + lane, 0, 0, kTagCountSketch, seed, 0);
+      codes[wave][4 * lane + 0] = countsketch_code(y.y0, (uint64_t)s1);
+      codes[wave][4 * lane + 1] = countsketch_code(y.y1, (uint64_t)s1);
+      codes[wave][4 * lane + 2] = countsketch_code(y.y2, (uint64_t)s1);
+      codes[wave][4 * lane + 3] = countsketch_code(y.y3, (uint64_t)s1);
+    }
+    wave_lds_sync();
+    const int rows = (int)((r_end - base) < kCsChunk ? (r_end - base) : kCsChunk);
+    for (int b0 = 0; b0 < rows; b0 += RB) {
+      const int rq = b0 + q;
+      const bool valid = rq < rows && c < n;
+      double v = valid ? V[(base + rq) * ldv + c] : 0.0;
+      const uint32_t code = rq < rows ? codes[wave][rq] : 0u;
+      if (code & 1u) v = -v;
+      const uint32_t bkt = code >> 1;
+      if constexpr (RB > 1) {
+        // combine rows of this batch with the same bucket into the lowest such row, in row order
+        bool leader = rq < rows;
+        double tot = v;
+#pragma unroll
+        for (int q2 = 0; q2 < RB; ++q2) {
+          const double v2 = shfl_d(v, q2 * NPL + c);
+          const int rq2 = b0 + q2;
+          const bool same = rq2 < rows && (codes[wave][rq2 < rows ? rq2 : 0] >> 1) == bkt;
+          if (same && q2 < q) leader = false;
+          if (same && q2 > q) tot += v2;
+        }
+        if (leader && c < n) mine[bkt * NPL + c] += tot;
+      } else {
+        if (valid) mine[bkt * NPL + c] += v;
+      }
+      wave_lds_sync();
+    }
+  }
+  __syncthreads();
+  // fixed-order sum of the four wave copies -> this workgroup's partial
+  double* out = parts + (int64_t)blockIdx.x * s1 * n;
+  for (int64_t i = threadIdx.x; i < s1 * n; i += blockDim.x) {
+    const int64_t b = i / n, cc = i % n;
+    const int64_t o = b * NPL + cc;
+    out[i] = ((w1[0][o] + w1[1][o]) + w1[2][o]) + w1[3][o];
+  }
+}
+
+hipError_t launch_countsketch_lds(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, uint64_t seed, double* parts,
+                                  int nparts, hipStream_t s) {
+  const dim3 grid((unsigned)nparts), block(256);
+  switch (npl_of(n)) {
+    case 8: hipLaunchKernelGGL(countsketch_lds_kernel<8>, grid, block, 0, s, V, ldv, m, n, s1, seed, parts); break;
+    case 16: hipLaunchKernelGGL(countsketch_lds_kernel<16>, grid, block, 0, s, V, ldv, m, n, s1, seed, parts); break;
+    case 32: hipLaunchKernelGGL(countsketch_lds_kernel<32>, grid, block, 0, s, V, ldv, m, n, s1, seed, parts); break;
+    case 64: hipLaunchKernelGGL(countsketch_lds_kernel<64>, grid, block, 0, s, V, ldv, m, n, s1, seed, parts); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Gaussian sketch GEMM (split over s1): Wpart[kc] = S2[:, chunk] W1[chunk, :].
+// ------------------------------------------------------------------------------------------
+constexpr int kGemmRows = 64;  // rows of S2 (and W) per workgroup
+constexpr int kGemmK = 16;     // k-step held in LDS
+
+template <int NPL>
+__global__ __launch_bounds__(256) void gauss_gemm_kernel(const double* __restrict__ W1, int n, int64_t s1, int64_t s2, uint64_t seed,
+                                                         double scale, int64_t kc_len, double* __restrict__ wpart) {
+  __shared__ double st[kGemmK][kGemmRows + 1];  // S2 tile [k][j]
+  __shared__ double wt[kGemmK][NPL];            // W1 tile [k][c]
+  constexpr int CPT = NPL / 4;                  // columns per thread
+  const int t = threadIdx.x;
+  const int jl = t % kGemmRows, cg = t / kGemmRows;
+  const int64_t kc = blockIdx.x, rb = blockIdx.y;
+  const int64_t k_beg = kc * kc_len;
+  const int64_t k_end = k_beg + kc_len < s1 ? k_beg + kc_len : s1;
+  double acc[CPT];
+#pragma unroll
+  for (int i = 0; i < CPT; ++i) acc[i] = 0.0;
+  for (int64_t k0 = k_beg; k0 < k_end; k0 += kGemmK) {
+    {  // S2 entries: thread -> (kk, j-block of 4)
+      const int kk = t % kGemmK, jb = t / kGemmK;  // jb in 0..15
+      const int64_t k = k0 + kk;
+      const int64_t jblk = rb * (kGemmRows / 4) + jb;
+      double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
+      if (k < k_end) {
+        const Block4 y = philox4x64_10((uint64_t)k, (uint64_t)jblk, 0, kTagGaussian, seed, 0);
+        box_muller(y.y0, y.y1, z0, z1);
+        box_muller(y.y2, y.y3, z2, z3);
+      }
+      const int64_t j = 4 * jblk;
+      st[kk][4 * jb + 0] = (k < k_end && j + 0 < s2) ? z0 * scale : 0.0;
+      st[kk][4 * jb + 1] = (k < k_end && j + 1 < s2) ? z1 * scale : 0.0;
+      st[kk][4 * jb + 2] = (k < k_end && j + 2 < s2) ? z2 * scale : 0.0;
+      st[kk][4 * jb + 3] = (k < k_end && j + 3 < s2) ? z3 * scale : 0.0;
+    }
+    for (int i = t; i < kGemmK * NPL; i += 256) {
+      const int kk = i / NPL, c = i % NPL;
+      const int64_t k = k0 + kk;
+      wt[kk][c] = (k < k_end && c < n) ? W1[k * n + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kGemmK; ++kk) {
+      const double sv = st[kk][jl];
+#pragma unroll
+      for (int i = 0; i < CPT; ++i) acc[i] = __builtin_fma(sv, wt[kk][cg + 4 * i], acc[i]);
+    }
+    __syncthreads();
+  }
+  const int64_t j = rb * kGemmRows + jl;
+  if (j < s2) {
+    double* out = wpart + (kc * s2 + j) * n;
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+      const int c = cg + 4 * i;
+      if (c < n) out[c] = acc[i];
+    }
+  }
+}
+
+hipError_t launch_gauss_gemm(const double* W1, int n, int64_t s1, int64_t s2, uint64_t seed, double scale, int64_t kc_len,
+                             int64_t nkc, double* wpart, hipStream_t s) {
+  const dim3 grid((unsigned)nkc, (unsigned)((s2 + kGemmRows - 1) / kGemmRows)), block(256);
+  const int npl = n <= 32 ? 32 : n <= 64 ? 64 : 128;
+  if (npl == 32)
+    hipLaunchKernelGGL(gauss_gemm_kernel<32>, grid, block, 0, s, W1, n, s1, s2, seed, scale, kc_len, wpart);
+  else if (npl == 64)
+    hipLaunchKernelGGL(gauss_gemm_kernel<64>, grid, block, 0, s, W1, n, s1, s2, seed, scale, kc_len, wpart);
+  else
+    hipLaunchKernelGGL(gauss_gemm_kernel<128>, grid, block, 0, s, W1, n, s1, s2, seed, scale, kc_len, wpart);
+  return hipGetLastError();
+}
+
+// Debug: a block of S2 entries.
+__global__ void gaussian_block_kernel(int64_t j0, int64_t nj, int64_t k0, int64_t nk, uint64_t seed, double scale, double* out) {
+  const int64_t total = nj * nk;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = j0 + i / nk, k = k0 + i % nk;
+    const Block4 y = philox4x64_10((uint64_t)k, (uint64_t)(j >> 2), 0, kTagGaussian, seed, 0);
+    double z0, z1;
+    if ((j & 3) < 2)
+      box_muller(y.y0, y.y1, z0, z1);
+    else
+      box_muller(y.y2, y.y3, z0, z1);
+    out[i] = ((j & 1) ? z1 : z0) * scale;
+  }
+}
+
+hipError_t launch_gaussian_block(int64_t j0, int64_t nj, int64_t k0, int64_t nk, uint64_t seed, double scale, double* out,
+                                 hipStream_t s) {
+  if (nj * nk <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gaussian_block_kernel, dim3(grid_for(nj * nk, 256)), dim3(256), 0, s, j0, nj, k0, nk, seed, scale, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Fixed-order sum of partials.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void reduce_parts_kernel(const double* __restrict__ parts, int64_t nparts, int64_t stride, int64_t len,
+                                                           double* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    int64_t p = 0;
+    for (; p + 8 <= nparts; p += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = parts[(p + u) * stride + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; p < nparts; ++p) acc += parts[p * stride + i];
+    out[i] = acc;
+  }
+}
+
+hipError_t launch_reduce_parts(const double* parts, int64_t nparts, int64_t stride, int64_t len, double* out, hipStream_t s) {
+  if (len <= 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(grid_for(len, 256, 2048)), dim3(256), 0, s, parts, nparts, stride, len, out);
+  return hipGetLastError();
+}
+
+}  // namespace rcqr

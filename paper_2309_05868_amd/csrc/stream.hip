@@ -1,0 +1,259 @@
+// The two streaming passes over V.
+//
+//  trsm_gram_kernel  Q0 = V R0^{-1} (Algorithm 1, step 3) fused with the Gram matrix
+//                    G = Q0^T Q0 (Algorithm 2, step 1 applied to Q0).  One lane owns one row of
+//                    V and solves x R0 = v by forward substitution (Section 5.2 analyses this
+//                    row by row; an explicit inverse of R0 is not used).  The wave's 64 solved
+//                    rows are transposed through LDS into FP64 MFMA operands and
+//                    G += X^T X is accumulated with v_mfma_f64_16x16x4f64 on the upper 16x16
+//                    blocks.  Each workgroup sums its waves in fixed order and writes one
+//                    partial; the workgroup count is fixed, so the summation order is too.
+//  final_kernel      Q = Q0 R1^{-1} (Algorithm 2, step 3 on Q0): recomputes the same Q0 row with
+//                    the same device function (bitwise identical to the Gram pass: explicit
+//                    FMAs, no implicit contraction) and solves with R1 by substitution.
+//
+// Rows are padded to NP columns; the padded R has an identity block, so padded columns stay
+// zero and contribute nothing.
+#include "device_common.h"
+#include "launch.h"
+
+namespace rcqr {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Returns 0, but the compiler cannot see that, and cannot compute it before `after` is
+// ready: a load at p + opaque_zero(after) is issued after the arithmetic that produced
+// `after` (no hoisting of the coefficient loads ahead of the work that precedes them), while p
+// keeps its address space and read-only provenance, so the load is still a scalar load.
+__device__ __forceinline__ int opaque_zero(double after) {
+  int z = 0;
+  asm volatile("" : "+s"(z) : "v"(after));
+  return z;
+}
+
+// x R = v for one row, R upper triangular and padded to NP columns, stored packed row by row
+// with the reciprocal of each diagonal entry in place of the entry:
+//   Rpk = [1/R00, R01, ..., R0,NP-1, 1/R11, R12, ..., 1/R(NP-1)(NP-1)].
+// Column-oriented forward substitution: x_k = v_k * (1/R_kk), then v_j -= x_k R_kj (j > k),
+// k ascending.  The coefficients are uniform across the wave and are streamed into scalar
+// registers eight at a time, two chunks ahead of use; a scheduling barrier per chunk keeps
+// the compiler from hoisting all of them at once.
+template <int NP>
+__device__ __forceinline__ void rowsolve(double (&x)[NP], const double* __restrict__ Rpk) {
+  constexpr int NV = NP * (NP + 1) / 2;
+  constexpr int NCH = (NV + 7) / 8;
+  constexpr int PD = 2;
+  double buf[PD + 1][8];
+#pragma unroll
+  for (int ch = 0; ch < PD; ++ch) {
+    if (ch < NCH) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) buf[ch][e] = (8 * ch + e < NV) ? Rpk[8 * ch + e] : 0.0;
+    }
+  }
+  int v = 0;
+  double last = x[0];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+#pragma unroll
+    for (int j = k; j < NP; ++j) {
+      if ((v & 7) == 0) {
+        __builtin_amdgcn_sched_barrier(0);
+        const int nxt = (v >> 3) + PD;
+        if (nxt < NCH) {
+          const double* src = Rpk + opaque_zero(last);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) buf[nxt % (PD + 1)][e] = (8 * nxt + e < NV) ? src[8 * nxt + e] : 0.0;
+        }
+      }
+      const double c = buf[(v >> 3) % (PD + 1)][v & 7];
+      if (j == k) {
+        x[k] = x[k] * c;
+        last = x[k];
+      } else {
+        x[j] = __builtin_fma(-x[k], c, x[j]);
+        last = x[j];
+      }
+      ++v;
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+int packed_len(int np) { return np * (np + 1) / 2; }
+
+// FULL: n == NP and rows are 16-byte aligned (V, Q aligned, even leading dimensions), so a row
+// moves as NP/2 unguarded 16-byte accesses.  Otherwise every column is guarded by c < n.
+template <int NP, bool FULL>
+__device__ __forceinline__ void load_row(double (&x)[NP], const double* __restrict__ V, int64_t row, int64_t m, int n,
+                                         int64_t ldv) {
+  const double* src = V + row * ldv;
+  if (row >= m) {
+#pragma unroll
+    for (int c = 0; c < NP; ++c) x[c] = 0.0;
+    return;
+  }
+  if constexpr (FULL) {
+    const double2* s2 = reinterpret_cast<const double2*>(src);
+#pragma unroll
+    for (int c = 0; c < NP / 2; ++c) {
+      const double2 v = s2[c];
+      x[2 * c] = v.x;
+      x[2 * c + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < NP; ++c) x[c] = c < n ? src[c] : 0.0;
+  }
+}
+
+template <int NP, bool FULL>
+__device__ __forceinline__ void store_row(const double (&x)[NP], double* __restrict__ Q, int64_t row, int n, int64_t ldq) {
+  double* dst = Q + row * ldq;
+  if constexpr (FULL) {
+    double2* d2 = reinterpret_cast<double2*>(dst);
+#pragma unroll
+    for (int c = 0; c < NP / 2; ++c) d2[c] = double2{x[2 * c], x[2 * c + 1]};
+  } else {
+#pragma unroll
+    for (int c = 0; c < NP; ++c)
+      if (c < n) dst[c] = x[c];
+  }
+}
+
+int gram_compact_len(int np) {
+  const int nb = np / 16;
+  return nb * (nb + 1) / 2 * 256;
+}
+
+template <int NP, bool FULL>
+__global__ __launch_bounds__(kGramThreads, 1) void trsm_gram_kernel(const double* __restrict__ V, int64_t m, int n, int64_t ldv,
+                                                                    const double* __restrict__ R0pk,
+                                                                    const int32_t* __restrict__ info, double* __restrict__ gpart,
+                                                                    double* __restrict__ q0, int64_t ldq) {
+  constexpr int NB = NP / 16;
+  constexpr int NBU = NB * (NB + 1) / 2;
+  constexpr int NW = kGramThreads / kWave;
+  __shared__ double xs[NW][16][kWave + 1];
+  __shared__ double gl[NBU * 256];
+  if (info[0] != 0) return;
+  const int wave = threadIdx.x / kWave;
+  const int lane = lane_id();
+  d4 acc[NBU];
+#pragma unroll
+  for (int i = 0; i < NBU; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const int64_t ntiles = (m + kWave - 1) / kWave;
+  for (int64_t t = (int64_t)blockIdx.x * NW + wave; t < ntiles; t += (int64_t)gridDim.x * NW) {
+    const int64_t row = t * kWave + lane;
+    double x[NP];
+    load_row<NP, FULL>(x, V, row, m, n, ldv);
+    rowsolve<NP>(x, R0pk);
+    if (q0 != nullptr && row < m) store_row<NP, FULL>(x, q0, row, n, ldq);
+    // transpose 16-column blocks through LDS into MFMA operands:
+    // F[a][s] (lane l) = X[4s + l/16][16a + l%16]
+    double F[NB][16];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c) xs[wave][c][lane] = x[16 * a + c];
+      wave_lds_sync();
+#pragma unroll
+      for (int s = 0; s < 16; ++s) F[a][s] = xs[wave][lane & 15][4 * s + (lane >> 4)];
+      wave_lds_sync();
+    }
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      int ab = 0;
+#pragma unroll
+      for (int a = 0; a < NB; ++a) {
+#pragma unroll
+        for (int b = a; b < NB; ++b) {
+          acc[ab] = __builtin_amdgcn_mfma_f64_16x16x4f64(F[a][s], F[b][s], acc[ab], 0, 0, 0);
+          ++ab;
+        }
+      }
+    }
+  }
+  // fixed-order sum of the waves' blocks; MFMA output element e of lane l is D[l/16 + 4e][l%16]
+  for (int w = 0; w < NW; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int ab = 0; ab < NBU; ++ab) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int idx = ab * 256 + ((lane >> 4) + 4 * e) * 16 + (lane & 15);
+          gl[idx] = (w == 0) ? acc[ab][e] : gl[idx] + acc[ab][e];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double* out = gpart + (int64_t)blockIdx.x * (NBU * 256);
+  for (int i = threadIdx.x; i < NBU * 256; i += kGramThreads) out[i] = gl[i];
+}
+
+template <int NP, bool APPLY_R1, bool FULL>
+__global__ __launch_bounds__(256) void final_kernel(const double* __restrict__ V, int64_t m, int n, int64_t ldv,
+                                                    const double* __restrict__ R0pk, const double* __restrict__ R1pk,
+                                                    const int32_t* __restrict__ info, double* __restrict__ Q, int64_t ldq) {
+  if (info[0] != 0) return;
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= m) return;
+  double x[NP];
+  load_row<NP, FULL>(x, V, row, m, n, ldv);
+  rowsolve<NP>(x, R0pk);
+  if constexpr (APPLY_R1) rowsolve<NP>(x, R1pk);
+  store_row<NP, FULL>(x, Q, row, n, ldq);
+}
+
+static bool full_rows(int np, int n, const void* a, int64_t lda, const void* b, int64_t ldb) {
+  const bool al = (reinterpret_cast<uintptr_t>(a) % 16 == 0) && (lda % 2 == 0);
+  const bool bl = b == nullptr || ((reinterpret_cast<uintptr_t>(b) % 16 == 0) && (ldb % 2 == 0));
+  return n == np && al && bl;
+}
+
+hipError_t launch_trsm_gram(int np, const double* V, int64_t m, int n, int64_t ldv, const double* r0pk, const int32_t* info,
+                            double* gpart, double* q0, int64_t ldq, hipStream_t s) {
+  const dim3 grid(kGramBlocks), block(kGramThreads);
+  const bool full = full_rows(np, n, V, ldv, q0, ldq);
+#define RCQR_GRAM(NPV)                                                                                                   \
+  if (full)                                                                                                              \
+    hipLaunchKernelGGL((trsm_gram_kernel<NPV, true>), grid, block, 0, s, V, m, n, ldv, r0pk, info, gpart, q0, ldq);    \
+  else                                                                                                                   \
+    hipLaunchKernelGGL((trsm_gram_kernel<NPV, false>), grid, block, 0, s, V, m, n, ldv, r0pk, info, gpart, q0, ldq);
+  switch (np) {
+    case 16: RCQR_GRAM(16) break;
+    case 32: RCQR_GRAM(32) break;
+    case 64: RCQR_GRAM(64) break;
+    default: return hipErrorInvalidValue;
+  }
+#undef RCQR_GRAM
+  return hipGetLastError();
+}
+
+hipError_t launch_final(int np, bool apply_r1, const double* V, int64_t m, int n, int64_t ldv, const double* r0pk,
+                        const double* r1pk, const int32_t* info, double* Q, int64_t ldq, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((m + 255) / 256)), block(256);
+  const bool full = full_rows(np, n, V, ldv, Q, ldq);
+#define RCQR_FINAL(NPV)                                                                                                    \
+  if (apply_r1 && full)                                                                                                    \
+    hipLaunchKernelGGL((final_kernel<NPV, true, true>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq);      \
+  else if (apply_r1)                                                                                                       \
+    hipLaunchKernelGGL((final_kernel<NPV, true, false>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq);     \
+  else if (full)                                                                                                           \
+    hipLaunchKernelGGL((final_kernel<NPV, false, true>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq);     \
+  else                                                                                                                     \
+    hipLaunchKernelGGL((final_kernel<NPV, false, false>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq);
+  switch (np) {
+    case 16: RCQR_FINAL(16) break;
+    case 32: RCQR_FINAL(32) break;
+    case 64: RCQR_FINAL(64) break;
+    default: return hipErrorInvalidValue;
+  }
+#undef RCQR_FINAL
+  return hipGetLastError();
+}
+
+}  // namespace rcqr

@@ -1,0 +1,87 @@
+"""The C-ABI library loads and exports every function include/rcqr.h declares (no GPU needed).
+
+Only host-side entry points are called here: workspace sizing, status strings, phase names and
+argument validation that fails before any device work.
+"""
+
+import ctypes
+import os
+
+import pytest
+
+import paper_2309_05868_amd as rc
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(rc.LIB_PATH):
+        from paper_2309_05868_amd import build
+        build.build()
+    return rc.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = rc.declared_functions()
+    assert {"rcqr_plan", "rcqr_factor", "rcqr_destroy", "rcqr_workspace_bytes", "rcqr_info"} <= set(names)
+    raw = ctypes.CDLL(rc.LIB_PATH)
+    missing = [nm for nm in names if not hasattr(raw, nm)]
+    assert not missing, missing
+    assert set(names) == set(rc._SIGNATURES), "binding signatures out of sync with the header"
+
+
+def test_workspace_bytes_and_shape_checks(lib):
+    ws = rc.workspace_bytes(10_000, 16, 512, 64)
+    assert ws > 512 * 16 * 8 and ws % 256 == 0
+    # CSR CountSketch needs per-row index storage; the LDS path does not
+    assert rc.workspace_bytes(2_000_000, 64, 8192, 256) > 2 * 4 * 2_000_000
+    assert rc.workspace_bytes(10, 16, 8, 16) == 0       # s1 < s2
+    assert rc.workspace_bytes(10, 16, 64, 8) == 0       # s2 < n
+    assert rc.workspace_bytes(8, 16, 64, 32) == 0       # m < n
+    assert rc.workspace_bytes(1000, 0, 64, 32) == 0     # n < 1
+    assert rc.workspace_bytes(10_000, 100, 20_000, 400) == 0  # n beyond the kernels
+    assert rc.workspace_bytes(2**31, 8, 128, 32) == 0   # row index must fit 31 bits
+
+
+def test_status_strings_and_phase_names(lib):
+    assert rc.status_string(rc.OK) == "ok"
+    assert "Cholesky" in rc.status_string(rc.E_CHOL)
+    assert "diagonal" in rc.status_string(rc.E_RANK)
+    names = [lib.rcqr_phase_name(i).decode() for i in range(6)]
+    assert names == ["countsketch", "gaussian", "householder", "trsm_gram", "cholesky", "final"]
+    assert lib.rcqr_phase_name(6).decode() == "?"
+
+
+def test_plan_rejects_bad_arguments_on_host(lib):
+    h = ctypes.c_void_p()
+    # null workspace, bad shapes, nonzero flags and misaligned workspace fail before any HIP call
+    assert lib.rcqr_plan(ctypes.byref(h), 1000, 16, 512, 64, 0, 0, None, 0, None) == rc.E_INVALID
+    assert lib.rcqr_plan(ctypes.byref(h), 1000, 16, 8, 64, 0, 0, ctypes.c_void_p(256), 1 << 30, None) == rc.E_INVALID
+    assert lib.rcqr_plan(ctypes.byref(h), 1000, 100, 20_000, 400, 0, 0, ctypes.c_void_p(256), 1 << 30, None) == rc.E_UNSUPPORTED
+    assert lib.rcqr_plan(ctypes.byref(h), 1000, 16, 512, 64, 0, 1, ctypes.c_void_p(256), 1 << 30, None) == rc.E_INVALID
+    assert lib.rcqr_plan(ctypes.byref(h), 1000, 16, 512, 64, 0, 0, ctypes.c_void_p(8), 1 << 30, None) == rc.E_INVALID
+    assert lib.rcqr_plan(None, 1000, 16, 512, 64, 0, 0, ctypes.c_void_p(256), 1 << 30, None) == rc.E_INVALID
+    # a plan with a fake (never touched) workspace pointer: I/O argument checks are host-side
+    ws = rc.workspace_bytes(1000, 16, 512, 64)
+    assert lib.rcqr_plan(ctypes.byref(h), 1000, 16, 512, 64, 0, 0, ctypes.c_void_p(1 << 20), ws, None) == rc.OK
+    try:
+        p = ctypes.c_void_p(4096)
+        assert lib.rcqr_factor(h, None, 16, p, 16, p, 16) == rc.E_INVALID
+        assert lib.rcqr_factor(h, p, 15, p, 16, p, 16) == rc.E_INVALID       # ldv < n
+        assert lib.rcqr_factor(h, p, 16, p, 32, p, 16) == rc.E_INVALID       # in place with ldq != ldv
+        assert lib.rcqr_factor(h, p, 16, p, 16, p, 8) == rc.E_INVALID        # ldr < n
+        assert lib.rcqr_sketch_hash(h, -1, 4, p, p) == rc.E_INVALID
+        cnt = ctypes.c_int32()
+        arr = (ctypes.c_float * 6)()
+        assert lib.rcqr_phase_times(h, arr, 6, ctypes.byref(cnt)) == rc.E_INVALID  # timing never enabled
+    finally:
+        assert lib.rcqr_destroy(h) == rc.OK
+    assert lib.rcqr_destroy(None) == rc.E_INVALID
+
+
+def test_binding_refuses_cpu_tensors(lib):
+    import torch
+    V = torch.zeros((100, 16), dtype=torch.float64)
+    with pytest.raises((TypeError, RuntimeError, AssertionError)):
+        p = rc.Plan.__new__(rc.Plan)
+        p.m, p.n = 100, 16
+        rc._check_matrix(V, 100, 16, "V")
