@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "librcqr.so")
 HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "rcqr.h")
 
 OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_HIP, E_RANK, E_CHOL = range(7)
-MAX_N = 64  # columns the current kernels accept (the ABI reserves up to 128)
+MAX_N = 128  # largest number of columns the kernels accept
 
 _lib = None
 

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "librcqr.so")
-SOURCES = ["sketch.hip", "smalldense.hip", "stream.hip", "rcqr.hip"]
+SOURCES = ["sketch.hip", "smalldense.hip", "stream.hip", "stream128.hip", "rcqr.hip"]
 ARCH = "gfx950"
 
 # -ffp-contract=off: every FMA in the kernels is written explicitly, so the Gram pass and the

@@ -64,4 +64,11 @@ hipError_t launch_trsm_gram(int np, const double* V, int64_t m, int n, int64_t l
 hipError_t launch_final(int np, bool apply_r1, const double* V, int64_t m, int n, int64_t ldv, const double* r0pk,
                         const double* r1pk, const int32_t* info, double* Q, int64_t ldq, hipStream_t s);
 
+// --- stream128.hip (65..128 columns; factor in the blocked packed format) --------------------
+// out = in R^{-1} row by row (out may alias in with the same leading dimension).
+hipError_t launch_solve128(const double* in, int64_t m, int n, int64_t ldin, const double* rbk, const int32_t* info, double* out,
+                           int64_t ldout, hipStream_t s);
+// Gram partials of Q0 (kGramBlocks compact partials of 36 upper 16x16 blocks).
+hipError_t launch_syrk128(const double* Q0, int64_t m, int n, int64_t ldq, const int32_t* info, double* gpart, hipStream_t s);
+
 }  // namespace rcqr

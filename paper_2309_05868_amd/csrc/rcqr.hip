@@ -107,7 +107,7 @@ Layout make_layout(const Shape& sh) {
 rcqr_status_t check_shape(int64_t m, int64_t n, int64_t s1, int64_t s2) {
   if (n < 1 || m < n || s2 < n || s1 < s2) return RCQR_E_INVALID;
   if (m >= kMaxRows || s1 >= kMaxRows) return RCQR_E_INVALID;
-  if (n > 64) return RCQR_E_UNSUPPORTED;
+  if (n > RCQR_MAX_N) return RCQR_E_UNSUPPORTED;
   return RCQR_OK;
 }
 
@@ -179,13 +179,32 @@ static rcqr_status_t run_householder(rcqr_plan_t p) {
   return RCQR_OK;
 }
 
-// G = (V Rp^{-1})^T (V Rp^{-1}) into the compact buffer.
-static rcqr_status_t run_gram(rcqr_plan_t p, const double* V, int64_t ldv, const double* rpk) {
+// G = (V Rp^{-1})^T (V Rp^{-1}) into the compact buffer.  Up to 64 columns Q0 is never stored
+// (the final pass recomputes it); for 65..128 columns Q0 is written into Q and read back.
+static rcqr_status_t run_gram(rcqr_plan_t p, const double* V, int64_t ldv, const double* rpk, double* Q, int64_t ldq) {
   const Shape& sh = p->sh;
   const int len = gram_compact_len(sh.np);
-  RCQR_TRY(launch_trsm_gram(sh.np, V, sh.m, (int)sh.n, ldv, rpk, p->at<int32_t>(p->L.info), p->at<double>(p->L.gpart), nullptr,
-                            0, p->stream));
+  const int32_t* info = p->at<int32_t>(p->L.info);
+  if (sh.np <= 64) {
+    RCQR_TRY(launch_trsm_gram(sh.np, V, sh.m, (int)sh.n, ldv, rpk, info, p->at<double>(p->L.gpart), nullptr, 0, p->stream));
+  } else {
+    RCQR_TRY(launch_solve128(V, sh.m, (int)sh.n, ldv, rpk, info, Q, ldq, p->stream));
+    RCQR_TRY(launch_syrk128(Q, sh.m, (int)sh.n, ldq, info, p->at<double>(p->L.gpart), p->stream));
+  }
   RCQR_TRY(launch_reduce_parts(p->at<double>(p->L.gpart), kGramBlocks, len, len, p->at<double>(p->L.gc), p->stream));
+  return RCQR_OK;
+}
+
+// Q = (V R0^{-1}) R1^{-1}: recomputed from V up to 64 columns, from the stored Q0 (in Q) above.
+static rcqr_status_t run_final(rcqr_plan_t p, const double* V, int64_t ldv, const double* r0pk, const double* r1pk, double* Q,
+                               int64_t ldq) {
+  const Shape& sh = p->sh;
+  const int32_t* info = p->at<int32_t>(p->L.info);
+  if (sh.np <= 64) {
+    RCQR_TRY(launch_final(sh.np, true, V, sh.m, (int)sh.n, ldv, r0pk, r1pk, info, Q, ldq, p->stream));
+  } else {
+    RCQR_TRY(launch_solve128(Q, sh.m, (int)sh.n, ldq, r1pk, info, Q, ldq, p->stream));
+  }
   return RCQR_OK;
 }
 
@@ -331,14 +350,14 @@ rcqr_status_t rcqr_factor(rcqr_plan_t p, const double* V, int64_t ldv, double* Q
   if (run_householder(p) != RCQR_OK) return RCQR_E_HIP;
   if (mark(p, 3) != RCQR_OK) return RCQR_E_HIP;
   // Algorithm 1, step 3 + Algorithm 2, step 1: Q0 = V R0^{-1}, G = Q0^T Q0
-  if (run_gram(p, V, ldv, p->at<double>(L.r0pk)) != RCQR_OK) return RCQR_E_HIP;
+  if (run_gram(p, V, ldv, p->at<double>(L.r0pk), Q, ldq) != RCQR_OK) return RCQR_E_HIP;
   if (mark(p, 4) != RCQR_OK) return RCQR_E_HIP;
   // Algorithm 2, step 2 and Algorithm 3, step 3: R1 = chol(G), R = R1 R0
   RCQR_TRY(launch_cholesky(p->at<double>(L.gc), n, sh.np, p->at<double>(L.r0), info, p->at<double>(L.g), p->at<double>(L.r1),
                            p->at<double>(L.r1pk), R, ldr, s));
   if (mark(p, 5) != RCQR_OK) return RCQR_E_HIP;
   // Algorithm 2, step 3 on Q0: Q = Q0 R1^{-1}
-  RCQR_TRY(launch_final(sh.np, true, V, sh.m, n, ldv, p->at<double>(L.r0pk), p->at<double>(L.r1pk), info, Q, ldq, s));
+  if (run_final(p, V, ldv, p->at<double>(L.r0pk), p->at<double>(L.r1pk), Q, ldq) != RCQR_OK) return RCQR_E_HIP;
   if (mark(p, 6) != RCQR_OK) return RCQR_E_HIP;
   if (p->cap > 0) ++p->recorded;
   return RCQR_OK;
@@ -355,14 +374,14 @@ rcqr_status_t rcqr_cholqr2(rcqr_plan_t p, const double* V, int64_t ldv, double* 
   RCQR_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(info), 16, 0u, s));
   // first cholQR: G = V^T V (R0 := I), Ra = chol(G)
   RCQR_TRY(launch_identity_factor(n, sh.np, p->at<double>(L.r0), p->at<double>(L.r0pk), s));
-  if (run_gram(p, V, ldv, p->at<double>(L.r0pk)) != RCQR_OK) return RCQR_E_HIP;
+  if (run_gram(p, V, ldv, p->at<double>(L.r0pk), Q, ldq) != RCQR_OK) return RCQR_E_HIP;
   RCQR_TRY(launch_cholesky(p->at<double>(L.gc), n, sh.np, p->at<double>(L.r0), info, p->at<double>(L.g), p->at<double>(L.ra),
                            p->at<double>(L.rapk), p->at<double>(L.rtmp), n, s));
   // second cholQR on Q0 = V Ra^{-1}: Rb = chol(Q0^T Q0), R = Rb Ra
-  if (run_gram(p, V, ldv, p->at<double>(L.rapk)) != RCQR_OK) return RCQR_E_HIP;
+  if (run_gram(p, V, ldv, p->at<double>(L.rapk), Q, ldq) != RCQR_OK) return RCQR_E_HIP;
   RCQR_TRY(launch_cholesky(p->at<double>(L.gc), n, sh.np, p->at<double>(L.rtmp), info, p->at<double>(L.g), p->at<double>(L.r1),
                            p->at<double>(L.r1pk), R, ldr, s));
-  RCQR_TRY(launch_final(sh.np, true, V, sh.m, n, ldv, p->at<double>(L.rapk), p->at<double>(L.r1pk), info, Q, ldq, s));
+  if (run_final(p, V, ldv, p->at<double>(L.rapk), p->at<double>(L.r1pk), Q, ldq) != RCQR_OK) return RCQR_E_HIP;
   return RCQR_OK;
 }
 
@@ -411,10 +430,15 @@ rcqr_status_t rcqr_q0_twice(rcqr_plan_t p, const double* V, int64_t ldv, double*
   if (p == nullptr || V == nullptr || Q0a == nullptr || Q0b == nullptr || ldv < p->sh.n || ldq < p->sh.n) return RCQR_E_INVALID;
   const Shape& sh = p->sh;
   const Layout& L = p->L;
-  RCQR_TRY(launch_trsm_gram(sh.np, V, sh.m, (int)sh.n, ldv, p->at<double>(L.r0pk), p->at<int32_t>(L.info), p->at<double>(L.gpart),
-                            Q0a, ldq, p->stream));
-  RCQR_TRY(launch_final(sh.np, false, V, sh.m, (int)sh.n, ldv, p->at<double>(L.r0pk), p->at<double>(L.r1pk), p->at<int32_t>(L.info),
-                        Q0b, ldq, p->stream));
+  if (sh.np <= 64) {
+    RCQR_TRY(launch_trsm_gram(sh.np, V, sh.m, (int)sh.n, ldv, p->at<double>(L.r0pk), p->at<int32_t>(L.info), p->at<double>(L.gpart),
+                              Q0a, ldq, p->stream));
+    RCQR_TRY(launch_final(sh.np, false, V, sh.m, (int)sh.n, ldv, p->at<double>(L.r0pk), p->at<double>(L.r1pk),
+                          p->at<int32_t>(L.info), Q0b, ldq, p->stream));
+  } else {  // Q0 is stored, not recomputed: both outputs come from the same solve
+    RCQR_TRY(launch_solve128(V, sh.m, (int)sh.n, ldv, p->at<double>(L.r0pk), p->at<int32_t>(L.info), Q0a, ldq, p->stream));
+    RCQR_TRY(launch_solve128(V, sh.m, (int)sh.n, ldv, p->at<double>(L.r0pk), p->at<int32_t>(L.info), Q0b, ldq, p->stream));
+  }
   return RCQR_OK;
 }
 

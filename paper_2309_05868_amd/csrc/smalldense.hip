@@ -127,14 +127,26 @@ hipError_t launch_qr_blocks(const double* in, int64_t ldin, int64_t p_total, int
 // Offset of row k in the packed np x np upper-triangular format.
 __device__ __forceinline__ int packed_row(int k, int np) { return k * np - k * (k - 1) / 2; }
 
-// Write entry (r, c), c >= r, of the identity-padded packed factor: v is R[r][c] for r, c < n.
+// Position of entry (r, c), c >= r, of an np x np factor in the layout the streaming passes
+// read: packed rows for np <= 64; for np = 128 the blocked layout
+// [R00 packed (64) | R01 dense 64 x 64 row-major | R11 packed (64)].
+__device__ __forceinline__ int factor_index(int np, int r, int c) {
+  if (np <= 64) return packed_row(r, np) + (c - r);
+  constexpr int H = 64, PK = H * (H + 1) / 2;
+  if (r < H && c < H) return packed_row(r, H) + (c - r);
+  if (r < H) return PK + r * H + (c - H);
+  return PK + H * H + packed_row(r - H, H) + (c - r);
+}
+
+// Write entry (r, c), c >= r, of the identity-padded factor: v is R[r][c] for r, c < n; the
+// diagonal is stored as its reciprocal.
 __device__ __forceinline__ void put_packed(double* pk, int np, int n, int r, int c, double v) {
   double out;
   if (r < n && c < n)
     out = (r == c) ? 1.0 / v : v;
   else
     out = (r == c) ? 1.0 : 0.0;
-  pk[packed_row(r, np) + (c - r)] = out;
+  pk[factor_index(np, r, c)] = out;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -264,6 +276,13 @@ __global__ __launch_bounds__(256) void cholesky_kernel(const double* __restrict_
 hipError_t launch_cholesky(const double* gcompact, int n, int np, const double* rprev, int32_t* info, double* g_out,
                            double* r1, double* r1pk, double* r_out, int64_t ldr, hipStream_t s) {
   const size_t lds = (size_t)n * n * sizeof(double);
+  static bool attr_set = false;  // G of 128 x 128 needs 128 KiB of dynamic LDS
+  if (!attr_set) {
+    const hipError_t e = hipFuncSetAttribute((const void*)cholesky_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             RCQR_MAX_N * RCQR_MAX_N * (int)sizeof(double));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
   hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(256), lds, s, gcompact, n, np, rprev, info, g_out, r1, r1pk, r_out, ldr);
   return hipGetLastError();
 }

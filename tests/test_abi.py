@@ -38,7 +38,8 @@ def test_workspace_bytes_and_shape_checks(lib):
     assert rc.workspace_bytes(10, 16, 64, 8) == 0       # s2 < n
     assert rc.workspace_bytes(8, 16, 64, 32) == 0       # m < n
     assert rc.workspace_bytes(1000, 0, 64, 32) == 0     # n < 1
-    assert rc.workspace_bytes(10_000, 100, 20_000, 400) == 0  # n beyond the kernels
+    assert rc.workspace_bytes(10_000, 100, 20_000, 400) > 0
+    assert rc.workspace_bytes(10_000, 129, 40_000, 600) == 0  # n beyond the kernels
     assert rc.workspace_bytes(2**31, 8, 128, 32) == 0   # row index must fit 31 bits
 
 
@@ -56,7 +57,7 @@ def test_plan_rejects_bad_arguments_on_host(lib):
     # null workspace, bad shapes, nonzero flags and misaligned workspace fail before any HIP call
     assert lib.rcqr_plan(ctypes.byref(h), 1000, 16, 512, 64, 0, 0, None, 0, None) == rc.E_INVALID
     assert lib.rcqr_plan(ctypes.byref(h), 1000, 16, 8, 64, 0, 0, ctypes.c_void_p(256), 1 << 30, None) == rc.E_INVALID
-    assert lib.rcqr_plan(ctypes.byref(h), 1000, 100, 20_000, 400, 0, 0, ctypes.c_void_p(256), 1 << 30, None) == rc.E_UNSUPPORTED
+    assert lib.rcqr_plan(ctypes.byref(h), 1000, 129, 40_000, 600, 0, 0, ctypes.c_void_p(256), 1 << 30, None) == rc.E_UNSUPPORTED
     assert lib.rcqr_plan(ctypes.byref(h), 1000, 16, 512, 64, 0, 1, ctypes.c_void_p(256), 1 << 30, None) == rc.E_INVALID
     assert lib.rcqr_plan(ctypes.byref(h), 1000, 16, 512, 64, 0, 0, ctypes.c_void_p(8), 1 << 30, None) == rc.E_INVALID
     assert lib.rcqr_plan(None, 1000, 16, 512, 64, 0, 0, ctypes.c_void_p(256), 1 << 30, None) == rc.E_INVALID

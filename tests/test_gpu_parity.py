@@ -80,7 +80,7 @@ def test_gaussian_entries_match_oracle():
 # (m, n, s1): LDS CountSketch (s1 * padded n <= 4096) and bucket-index CountSketch, including
 # buckets longer than one sort window (m / s1 > 2048).
 CS_CASES = [(5000, 8, 128), (10_000, 16, 256), (20_001, 16, 512), (50_000, 64, 8192), (3001, 32, 2048),
-            (600_000, 64, 100), (9999, 50, 700)]
+            (600_000, 64, 100), (9999, 50, 700), (20_000, 128, 1000), (4321, 100, 333)]
 
 
 @pytest.mark.parametrize("m,n,s1", CS_CASES)
@@ -96,7 +96,8 @@ def test_countsketch_integer_bit_exact(m, n, s1):
 
 
 @pytest.mark.parametrize("m,n,s1,s2,kappa", [(10_000, 16, 512, 64, 1e4), (5000, 8, 128, 32, 1e2), (40_000, 64, 8192, 256, 1e6),
-                                              (3001, 32, 2048, 128, 1e3), (9999, 50, 700, 100, 1e5), (777, 10, 40, 20, 1e6)])
+                                              (3001, 32, 2048, 128, 1e3), (9999, 50, 700, 100, 1e5), (777, 10, 40, 20, 1e6),
+                                              (20_000, 128, 2048, 512, 1e6), (7000, 100, 1000, 300, 1e5)])
 def test_sketches_R0_and_R_match_oracle(m, n, s1, s2, kappa):
     say("rand_cholqr parity", m, n, s1, s2, kappa)
     seed = 11
@@ -123,7 +124,8 @@ def test_sketches_R0_and_R_match_oracle(m, n, s1, s2, kappa):
 
 
 @pytest.mark.parametrize("m,n,s1,s2,kappa", [(10_000, 16, 512, 64, 1e15), (20_000, 64, 8192, 256, 1e12), (30_000, 8, 128, 32, 1e15),
-                                              (12_345, 32, 2048, 128, 1e8), (5000, 24, 1152, 96, 1e14)])
+                                              (12_345, 32, 2048, 128, 1e8), (5000, 24, 1152, 96, 1e14),
+                                              (30_000, 128, 32768, 512, 1e15), (9000, 72, 10368, 288, 1e12)])
 def test_ill_conditioned_bounds(m, n, s1, s2, kappa):
     say("ill conditioned", m, n, s1, s2, kappa)
     V = synth.make_V(m, n, kappa, seed=3)
@@ -141,8 +143,9 @@ def test_ill_conditioned_bounds(m, n, s1, s2, kappa):
     assert st == 0 and rel(R0, R0o) <= 1e-12
 
 
-def test_q0_recompute_is_bitwise_identical_and_runs_are_deterministic():
-    m, n, s1, s2 = 30_000, 64, 8192, 256
+@pytest.mark.parametrize("n", [64, 16, 128])
+def test_q0_recompute_is_bitwise_identical_and_runs_are_deterministic(n):
+    m, s1, s2 = 30_000, 2 * n * n, 4 * n
     V = dev(synth.make_V(m, n, 1e12, seed=9))
     with rc.Plan(m, n, s1, s2, seed=9) as p:
         Qa, Ra = p.factor(V)
