@@ -49,6 +49,26 @@ def phase_model(name, m, n):
     return None, None
 
 
+def gram_accurate(Q, chunk=4096):
+    """Q^T Q summed accurately: exact-size chunk Grams (K = chunk) added pairwise.
+
+    A single GEMM over K = m rows accumulates long chains; at m = 2e6 its error (a few 1e-14
+    relative) would dominate an orthogonality error of order n u.
+    """
+    import torch
+
+    m, n = Q.shape
+    pad = (-m) % chunk
+    Qp = torch.cat([Q, Q.new_zeros(pad, n)]) if pad else Q
+    blocks = Qp.reshape(-1, chunk, n)
+    parts = torch.bmm(blocks.transpose(1, 2).contiguous(), blocks)
+    while parts.shape[0] > 1:
+        if parts.shape[0] % 2:
+            parts = torch.cat([parts, torch.zeros_like(parts[:1])])
+        parts = parts[0::2] + parts[1::2]
+    return parts[0]
+
+
 def cpu_baseline(wl, sample_rows):
     """The oracle as it stands, single-threaded, on a row-scaled sample of the workload."""
     from threadpoolctl import threadpool_limits
@@ -78,6 +98,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=100_000)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device-to-device copy of V's size (HBM counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -90,6 +112,16 @@ def main():
     import paper_2309_05868_amd as rc
     import synth
 
+    if args.calibrate_copy:
+        nbytes = WORKLOAD["m"] * WORKLOAD["n"] * 8
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
+                          "copies": args.steps}), flush=True)
+        return
     if not os.path.exists(rc.LIB_PATH):
         from paper_2309_05868_amd import build
         build.build()
@@ -127,7 +159,7 @@ def main():
 
     # accuracy of the timed result
     eye = torch.eye(n, dtype=torch.float64, device=dev)
-    orth = torch.linalg.norm(eye - Q.T @ Q).item()
+    orth = torch.linalg.norm(eye - gram_accurate(Q)).item()
     res = (torch.linalg.norm(V - Q @ R) / torch.linalg.norm(V)).item()
     tgt = 10 * n * U_PAPER
 

@@ -10,12 +10,17 @@ namespace rcqr {
 // --- sketch.hip --------------------------------------------------------------------------
 hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t s);
 hipError_t launch_fill_f64(double* p, int64_t count, double value, hipStream_t s);
-// codes[i] = (h(i) << 1) | signbit(i) for i < m; counts[h(i)] += 1 when counts != nullptr.
-hipError_t launch_hash_codes(int64_t m, int64_t s1, uint64_t seed, uint32_t* codes, uint32_t* counts, hipStream_t s);
-// offsets[0..s1] = exclusive scan of counts; cursor[b] = offsets[b].
+// Bucket index of S1 over `nchunk` contiguous row chunks (one workgroup each):
+//   hash_hist:  codes[i] = (h(i) << 1) | signbit(i); hist[chunk][b] = rows of the chunk in bucket b
+//   colscan:    hist[chunk][b] <- rows of bucket b in earlier chunks; counts[b] = bucket size
+//   scan:       offsets[0..s1] = exclusive scan of counts (cursor[b] = offsets[b] if non-null)
+//   scatter:    entries[offsets[b] + hist[chunk][b] + k] = (i << 1) | signbit(i)
+int64_t bucket_chunk_rows(int64_t m, int nchunk);
+hipError_t launch_hash_hist(int64_t m, int64_t s1, uint64_t seed, int nchunk, uint32_t* codes, uint32_t* hist, hipStream_t s);
+hipError_t launch_hist_colscan(int nchunk, int64_t s1, uint32_t* hist, uint32_t* counts, hipStream_t s);
 hipError_t launch_bucket_scan(const uint32_t* counts, int64_t s1, uint32_t* offsets, uint32_t* cursor, hipStream_t s);
-// entries[cursor[h(i)]++] = (i << 1) | signbit(i).
-hipError_t launch_bucket_scatter(int64_t m, const uint32_t* codes, uint32_t* cursor, uint32_t* entries, hipStream_t s);
+hipError_t launch_bucket_scatter(int64_t m, int64_t s1, int nchunk, const uint32_t* codes, const uint32_t* offsets, uint32_t* hist,
+                                 uint32_t* entries, hipStream_t s);
 // W1[b, :] = sum over the bucket's rows (ascending row order) of sign * V[row, :].
 hipError_t launch_bucket_gather(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, const uint32_t* offsets,
                                 const uint32_t* entries, double* W1, hipStream_t s);

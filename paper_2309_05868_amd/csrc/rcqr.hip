@@ -28,7 +28,7 @@ int padded_cols(int64_t n) {
 }
 
 struct Layout {
-  size_t info, w1, csparts, codes, counts, offsets, cursor, entries, wpart, w, qra, qrb, r0, r0pk, gpart, gc, g, r1, r1pk,
+  size_t info, w1, csparts, codes, counts, offsets, hist, entries, wpart, w, qra, qrb, r0, r0pk, gpart, gc, g, r1, r1pk,
       ra, rapk, rtmp, total;
 };
 
@@ -37,6 +37,7 @@ struct Shape {
   int np;
   bool lds_cs;
   int cs_parts;
+  int nchunk;  // row chunks of the bucket index build
   int64_t kc_len, nkc;
   int64_t qr_blocks0;
 };
@@ -50,6 +51,12 @@ Shape make_shape(int64_t m, int64_t n, int64_t s1, int64_t s2) {
   sh.np = padded_cols(n);
   sh.lds_cs = countsketch_lds_fits(s1, (int)n);
   sh.cs_parts = sh.lds_cs ? countsketch_lds_parts(m) : 0;
+  // bucket index: chunks of at least 4096 rows, at most 256, histogram matrix <= 2^26 entries
+  int64_t nch = (m + 4095) / 4096;
+  if (nch > 256) nch = 256;
+  const int64_t cap_ch = ((int64_t)1 << 26) / s1;
+  if (nch > cap_ch) nch = cap_ch;
+  sh.nchunk = nch < 1 ? 1 : (int)nch;
   // Gaussian GEMM split over s1: about 512 workgroups, partials capped at 16 MiB
   const int64_t nrb = (s2 + 63) / 64;
   int64_t nkc = 512 / nrb;
@@ -83,7 +90,7 @@ Layout make_layout(const Shape& sh) {
   L.codes = take(mm * 4);
   L.counts = take(ss * 4);
   L.offsets = take(sh.lds_cs ? 0 : (ss + 1) * 4);
-  L.cursor = take(ss * 4);
+  L.hist = take(sh.lds_cs ? 0 : (size_t)sh.nchunk * ss * 4);
   L.entries = take(mm * 4);
   L.wpart = take((size_t)sh.nkc * sh.s2 * n * 8);
   L.w = take((size_t)sh.s2 * n * 8);
@@ -328,13 +335,13 @@ rcqr_status_t rcqr_factor(rcqr_plan_t p, const double* V, int64_t ldv, double* Q
   } else {
     uint32_t* counts = p->at<uint32_t>(L.counts);
     uint32_t* offsets = p->at<uint32_t>(L.offsets);
-    uint32_t* cursor = p->at<uint32_t>(L.cursor);
+    uint32_t* hist = p->at<uint32_t>(L.hist);
     uint32_t* codes = p->at<uint32_t>(L.codes);
     uint32_t* entries = p->at<uint32_t>(L.entries);
-    RCQR_TRY(launch_fill_u32(counts, sh.s1, 0u, s));
-    RCQR_TRY(launch_hash_codes(sh.m, sh.s1, p->seed, codes, counts, s));
-    RCQR_TRY(launch_bucket_scan(counts, sh.s1, offsets, cursor, s));
-    RCQR_TRY(launch_bucket_scatter(sh.m, codes, cursor, entries, s));
+    RCQR_TRY(launch_hash_hist(sh.m, sh.s1, p->seed, sh.nchunk, codes, hist, s));
+    RCQR_TRY(launch_hist_colscan(sh.nchunk, sh.s1, hist, counts, s));
+    RCQR_TRY(launch_bucket_scan(counts, sh.s1, offsets, nullptr, s));
+    RCQR_TRY(launch_bucket_scatter(sh.m, sh.s1, sh.nchunk, codes, offsets, hist, entries, s));
     RCQR_TRY(launch_bucket_gather(V, ldv, sh.m, n, sh.s1, offsets, entries, W1, s));
   }
   if (mark(p, 1) != RCQR_OK) return RCQR_E_HIP;

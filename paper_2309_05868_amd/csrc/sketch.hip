@@ -45,36 +45,72 @@ hipError_t launch_fill_f64(double* p, int64_t count, double value, hipStream_t s
 }
 
 // ------------------------------------------------------------------------------------------
-// CountSketch hash: one Philox block serves rows 4q .. 4q+3.
+// CountSketch hash and per-chunk bucket histograms.  Rows are split into `nchunk` contiguous
+// chunks (a multiple of 4 rows each, one workgroup per chunk); one Philox block serves rows
+// 4q .. 4q+3.  hist[chunk][b] = number of rows of the chunk in bucket b.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void hash_codes_kernel(int64_t m, uint64_t s1, uint64_t seed, uint32_t* __restrict__ codes,
-                                                         uint32_t* __restrict__ counts) {
-  const int64_t nq = (m + 3) / 4;
-  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
-    const Block4 y = philox4x64_10((uint64_t)q, 0, 0, kTagCountSketch, seed, 0);
-    const uint32_t c0 = countsketch_code(y.y0, s1), c1 = countsketch_code(y.y1, s1);
-    const uint32_t c2 = countsketch_code(y.y2, s1), c3 = countsketch_code(y.y3, s1);
-    const int64_t r = 4 * q;
-    if (r + 3 < m) {
-      *reinterpret_cast<uint4*>(codes + r) = make_uint4(c0, c1, c2, c3);
+constexpr int kHistLds = 16384;  // buckets counted in LDS; above this, in the chunk's global row
+
+int64_t bucket_chunk_rows(int64_t m, int nchunk) { return ((m + nchunk - 1) / nchunk + 3) / 4 * 4; }
+
+__global__ __launch_bounds__(256) void hash_hist_kernel(int64_t m, uint64_t s1, uint64_t seed, int64_t chunk_rows, uint32_t* __restrict__ codes,
+                                                        uint32_t* __restrict__ hist) {
+  __shared__ uint32_t lh[kHistLds];
+  const bool in_lds = s1 <= (uint64_t)kHistLds;
+  uint32_t* gh = hist + (int64_t)blockIdx.x * (int64_t)s1;
+  if (in_lds) {
+    for (int64_t b = threadIdx.x; b < (int64_t)s1; b += blockDim.x) lh[b] = 0u;
+  } else {
+    for (int64_t b = threadIdx.x; b < (int64_t)s1; b += blockDim.x) gh[b] = 0u;
+  }
+  __syncthreads();
+  const int64_t r_beg = (int64_t)blockIdx.x * chunk_rows;
+  const int64_t r_end = r_beg + chunk_rows < m ? r_beg + chunk_rows : m;
+  for (int64_t r = r_beg + 4 * (int64_t)threadIdx.x; r < r_end; r += 4 * (int64_t)blockDim.x) {
+    const Block4 y = philox4x64_10((uint64_t)(r >> 2), 0, 0, kTagCountSketch, seed, 0);
+    const uint32_t c[4] = {countsketch_code(y.y0, s1), countsketch_code(y.y1, s1), countsketch_code(y.y2, s1),
+                           countsketch_code(y.y3, s1)};
+    if (r + 3 < r_end) {
+      *reinterpret_cast<uint4*>(codes + r) = make_uint4(c[0], c[1], c[2], c[3]);
     } else {
-      codes[r] = c0;
-      if (r + 1 < m) codes[r + 1] = c1;
-      if (r + 2 < m) codes[r + 2] = c2;
+      for (int u = 0; u < 4 && r + u < r_end; ++u) codes[r + u] = c[u];
     }
-    if (counts) {
-      atomicAdd(counts + (c0 >> 1), 1u);
-      if (r + 1 < m) atomicAdd(counts + (c1 >> 1), 1u);
-      if (r + 2 < m) atomicAdd(counts + (c2 >> 1), 1u);
-      if (r + 3 < m) atomicAdd(counts + (c3 >> 1), 1u);
+    for (int u = 0; u < 4 && r + u < r_end; ++u) {
+      if (in_lds)
+        atomicAdd(&lh[c[u] >> 1], 1u);
+      else
+        atomicAdd(&gh[c[u] >> 1], 1u);
     }
+  }
+  if (in_lds) {
+    __syncthreads();
+    for (int64_t b = threadIdx.x; b < (int64_t)s1; b += blockDim.x) gh[b] = lh[b];
   }
 }
 
-hipError_t launch_hash_codes(int64_t m, int64_t s1, uint64_t seed, uint32_t* codes, uint32_t* counts, hipStream_t s) {
-  const int64_t nq = (m + 3) / 4;
-  if (nq <= 0) return hipSuccess;
-  hipLaunchKernelGGL(hash_codes_kernel, dim3(grid_for(nq, 256, 8192)), dim3(256), 0, s, m, (uint64_t)s1, seed, codes, counts);
+hipError_t launch_hash_hist(int64_t m, int64_t s1, uint64_t seed, int nchunk, uint32_t* codes, uint32_t* hist, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(hash_hist_kernel, dim3(nchunk), dim3(256), 0, s, m, (uint64_t)s1, seed, bucket_chunk_rows(m, nchunk), codes, hist);
+  return hipGetLastError();
+}
+
+// hist[chunk][b] <- rows of bucket b in earlier chunks (exclusive scan down each column);
+// counts[b] <- total rows of bucket b.
+__global__ __launch_bounds__(256) void hist_colscan_kernel(int nchunk, int64_t s1, uint32_t* __restrict__ hist, uint32_t* __restrict__ counts) {
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < s1; b += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t run = 0;
+    for (int c = 0; c < nchunk; ++c) {
+      uint32_t* h = hist + (int64_t)c * s1 + b;
+      const uint32_t v = *h;
+      *h = run;
+      run += v;
+    }
+    counts[b] = run;
+  }
+}
+
+hipError_t launch_hist_colscan(int nchunk, int64_t s1, uint32_t* hist, uint32_t* counts, hipStream_t s) {
+  hipLaunchKernelGGL(hist_colscan_kernel, dim3(grid_for(s1, 256, 2048)), dim3(256), 0, s, nchunk, s1, hist, counts);
   return hipGetLastError();
 }
 
@@ -119,7 +155,7 @@ __global__ __launch_bounds__(1024) void bucket_scan_kernel(const uint32_t* __res
     const uint32_t incl = part[threadIdx.x] + carry;
     if (i < s1) {
       offsets[i] = incl - v;
-      cursor[i] = incl - v;
+      if (cursor) cursor[i] = incl - v;
     }
     __syncthreads();
     if (threadIdx.x == 1023) carry = incl;
@@ -133,18 +169,34 @@ hipError_t launch_bucket_scan(const uint32_t* counts, int64_t s1, uint32_t* offs
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void bucket_scatter_kernel(int64_t m, const uint32_t* __restrict__ codes,
-                                                             uint32_t* __restrict__ cursor, uint32_t* __restrict__ entries) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t code = codes[i];
-    const uint32_t pos = atomicAdd(cursor + (code >> 1), 1u);
-    entries[pos] = ((uint32_t)i << 1) | (code & 1u);
+// entries[offsets[b] + base(chunk, b) + k] = (row << 1) | signbit for the k-th row of the chunk
+// in bucket b (k from an LDS counter; the order inside a chunk is whatever the atomics give,
+// which the gather's sort removes).
+__global__ __launch_bounds__(256) void bucket_scatter_kernel(int64_t m, int64_t s1, int64_t chunk_rows, const uint32_t* __restrict__ codes,
+                                                             const uint32_t* __restrict__ offsets, uint32_t* __restrict__ hist,
+                                                             uint32_t* __restrict__ entries) {
+  __shared__ uint32_t cur[kHistLds];
+  const bool in_lds = s1 <= (int64_t)kHistLds;
+  uint32_t* gh = hist + (int64_t)blockIdx.x * s1;
+  if (in_lds) {
+    for (int64_t b = threadIdx.x; b < s1; b += blockDim.x) cur[b] = offsets[b] + gh[b];
+    __syncthreads();
+  }
+  const int64_t r_beg = (int64_t)blockIdx.x * chunk_rows;
+  const int64_t r_end = r_beg + chunk_rows < m ? r_beg + chunk_rows : m;
+  for (int64_t r = r_beg + threadIdx.x; r < r_end; r += blockDim.x) {
+    const uint32_t code = codes[r];
+    const uint32_t b = code >> 1;
+    const uint32_t pos = in_lds ? atomicAdd(&cur[b], 1u) : offsets[b] + atomicAdd(&gh[b], 1u);
+    entries[pos] = ((uint32_t)r << 1) | (code & 1u);
   }
 }
 
-hipError_t launch_bucket_scatter(int64_t m, const uint32_t* codes, uint32_t* cursor, uint32_t* entries, hipStream_t s) {
+hipError_t launch_bucket_scatter(int64_t m, int64_t s1, int nchunk, const uint32_t* codes, const uint32_t* offsets, uint32_t* hist,
+                                 uint32_t* entries, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(bucket_scatter_kernel, dim3(grid_for(m, 256, 8192)), dim3(256), 0, s, m, codes, cursor, entries);
+  hipLaunchKernelGGL(bucket_scatter_kernel, dim3(nchunk), dim3(256), 0, s, m, s1, bucket_chunk_rows(m, nchunk), codes, offsets, hist,
+                     entries);
   return hipGetLastError();
 }
 
@@ -182,31 +234,32 @@ __device__ __forceinline__ void gather_rows(const uint32_t* keys, int cnt, const
   const int g = NPL >= 64 ? 0 : lane / NPL;
   const int c = NPL >= 64 ? lane : lane % NPL;
   int e = g;
-  // four rows in flight, added in entry order
-  for (; e + 3 * G < cnt; e += 4 * G) {
-    const uint32_t k0 = keys[e], k1 = keys[e + G], k2 = keys[e + 2 * G], k3 = keys[e + 3 * G];
-    if constexpr (NPL > 64) {
-      double v[4][2];
-      const uint32_t kk[4] = {k0, k1, k2, k3};
+  // eight rows in flight, added in entry order
+  constexpr int U = 8;
+  for (; e + (U - 1) * G < cnt; e += U * G) {
+    uint32_t kk[U];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) kk[u] = keys[e + u * G];
+    if constexpr (NPL > 64) {
+      double v[U][2];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
         const double* row = V + (int64_t)(kk[u] >> 1) * ldv;
         v[u][0] = c < n ? row[c] : 0.0;
         v[u][1] = c + 64 < n ? row[c + 64] : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < U; ++u) {
         const bool neg = kk[u] & 1u;
         acc[0] += neg ? -v[u][0] : v[u][0];
         acc[1] += neg ? -v[u][1] : v[u][1];
       }
     } else {
-      const uint32_t kk[4] = {k0, k1, k2, k3};
-      double v[4];
+      double v[U];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = c < n ? V[(int64_t)(kk[u] >> 1) * ldv + c] : 0.0;
+      for (int u = 0; u < U; ++u) v[u] = c < n ? V[(int64_t)(kk[u] >> 1) * ldv + c] : 0.0;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[0] += (kk[u] & 1u) ? -v[u] : v[u];
+      for (int u = 0; u < U; ++u) acc[0] += (kk[u] & 1u) ? -v[u] : v[u];
     }
   }
   for (; e < cnt; e += G) {
@@ -511,22 +564,33 @@ hipError_t launch_gaussian_block(int64_t j0, int64_t nj, int64_t k0, int64_t nk,
 }
 
 // ------------------------------------------------------------------------------------------
-// Fixed-order sum of partials.
+// Fixed-order sum of partials, compensated (Neumaier's variant of Kahan summation): the
+// rounding error of each addition is recovered exactly (TwoSum) and added back at the end, so
+// the result does not degrade with the number of partials.
 // ------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void reduce_parts_kernel(const double* __restrict__ parts, int64_t nparts, int64_t stride, int64_t len,
                                                            double* __restrict__ out) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x) {
-    double acc = 0.0;
+    double sum = 0.0, comp = 0.0;
     int64_t p = 0;
     for (; p + 8 <= nparts; p += 8) {
       double v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) v[u] = parts[(p + u) * stride + i];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc += v[u];
+      for (int u = 0; u < 8; ++u) {
+        const double t = sum + v[u];
+        comp += (fabs(sum) >= fabs(v[u])) ? ((sum - t) + v[u]) : ((v[u] - t) + sum);
+        sum = t;
+      }
     }
-    for (; p < nparts; ++p) acc += parts[p * stride + i];
-    out[i] = acc;
+    for (; p < nparts; ++p) {
+      const double x = parts[p * stride + i];
+      const double t = sum + x;
+      comp += (fabs(sum) >= fabs(x)) ? ((sum - t) + x) : ((x - t) + sum);
+      sum = t;
+    }
+    out[i] = sum + comp;
   }
 }
 

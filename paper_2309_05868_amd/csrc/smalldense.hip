@@ -18,21 +18,33 @@ namespace rcqr {
 // ------------------------------------------------------------------------------------------
 // Householder QR of a p x n block (p <= 256), matrix held in registers.
 // Thread layout: column c = t / TPC, row group rg = t % TPC; a thread owns rows rg + TPC*e.
-// The TPC threads of one column are consecutive lanes of one wave (TPC <= 64, power of two),
-// so reductions over a column are wave shuffles; one barrier per reflector publishes v.
+// The TPC threads of a column are consecutive lanes of one wave, so column reductions are wave
+// shuffles, and the CPW = 64 / TPC columns of a wave form a panel.  Panel by panel: the owning
+// wave computes the panel's reflectors one after another (each applied at once to the panel's
+// later columns), with only wave-level LDS ordering; after one workgroup barrier every later
+// column applies the panel's reflectors in order.  Reflector j maps column j's x = A[j:, j] to
+// beta e1 with beta = -sign(x0) ||x||, H = I - tau v v^T, v[0] = 1.
 // ------------------------------------------------------------------------------------------
 constexpr int kQrMaxRows = 256;
 
-template <int NPAD>
-__global__ __launch_bounds__(NPAD * (1024 / NPAD < 64 ? 1024 / NPAD : 64)) void qr_block_kernel(const double* __restrict__ in, int64_t ldin,
-                                                                                                  int64_t p_total, int64_t rows_per_block, int n,
-                                                                                                  double* __restrict__ out) {
-  constexpr int TPC = 1024 / NPAD < 64 ? 1024 / NPAD : 64;
+template <int TPC>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int off = TPC / 2; off > 0; off >>= 1) v += shfl_xor_d(v, off);
+  return v;
+}
+
+template <int NPAD, int TPC>
+__global__ __launch_bounds__(NPAD * TPC) void qr_block_kernel(const double* __restrict__ in, int64_t ldin, int64_t p_total,
+                                                             int64_t rows_per_block, int n, double* __restrict__ out) {
+  static_assert(TPC <= 64 && (64 % TPC) == 0, "a column's threads must sit in one wave");
   constexpr int EPT = kQrMaxRows / TPC;
-  __shared__ double vbuf[2][kQrMaxRows];
-  __shared__ double taub[2];
+  constexpr int CPW = 64 / TPC;  // columns per wave = panel width
+  __shared__ double vbuf[2][CPW][kQrMaxRows];
+  __shared__ double taub[2][CPW];
   const int t = threadIdx.x;
   const int c = t / TPC, rg = t % TPC;
+  const int wave = t / kWave;
   const int64_t r_beg = (int64_t)blockIdx.x * rows_per_block;
   const int64_t p64 = p_total - r_beg < rows_per_block ? p_total - r_beg : rows_per_block;
   const int p = (int)p64;
@@ -43,60 +55,65 @@ __global__ __launch_bounds__(NPAD * (1024 / NPAD < 64 ? 1024 / NPAD : 64)) void 
     const int r = rg + TPC * e;
     a[e] = (r < p && c < n) ? A0[(int64_t)r * ldin + c] : 0.0;
   }
-  const int lane = lane_id();
-  const int group_base = lane & ~(TPC - 1);
   const int steps = n < p ? n : p;
-  for (int j = 0; j < steps; ++j) {
-    const int buf = j & 1;
-    if (c == j) {
-      double ss = 0.0, alpha = 0.0;
+  // apply reflector (vb, tau) with leading row j to this thread's column
+  auto apply = [&](const double* vb, double tau, int j) {
+    double d = 0.0;
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const int r = rg + TPC * e;
-        if (r > j) ss = __builtin_fma(a[e], a[e], ss);
-        if (r == j) alpha = a[e];
-      }
-      for (int off = TPC / 2; off > 0; off >>= 1) {
-        ss += shfl_xor_d(ss, off);
-        alpha += shfl_xor_d(alpha, off);  // only the owner of row j holds a nonzero term
-      }
-      const double xnorm = sqrt(ss);
-      double tau = 0.0, beta = alpha, denom = 1.0;
-      if (xnorm != 0.0) {
-        beta = -copysign(hypot(alpha, xnorm), alpha);
-        tau = (beta - alpha) / beta;
-        denom = alpha - beta;
-      }
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const int r = rg + TPC * e;
-        if (r == j) {
-          vbuf[buf][r] = 1.0;
-          a[e] = beta;
-        } else if (r > j) {
-          vbuf[buf][r] = xnorm != 0.0 ? a[e] / denom : 0.0;
-          a[e] = 0.0;
-        }
-      }
-      if (rg == 0) taub[buf] = tau;
+    for (int e = 0; e < EPT; ++e) {
+      const int r = rg + TPC * e;
+      if (r >= j && r < p) d = __builtin_fma(vb[r], a[e], d);
     }
-    (void)group_base;
+    d = group_sum<TPC>(d);
+    const double tw = tau * d;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int r = rg + TPC * e;
+      if (r >= j && r < p) a[e] = __builtin_fma(-tw, vb[r], a[e]);
+    }
+  };
+  for (int q = 0, pi = 0; q < steps; q += CPW, ++pi) {
+    const int buf = pi & 1;
+    const int qend = q + CPW < steps ? q + CPW : steps;
+    if (wave == q / CPW) {
+      for (int j = q; j < qend; ++j) {
+        const int jj = j - q;
+        if (c == j) {
+          double ss = 0.0, alpha = 0.0;
+#pragma unroll
+          for (int e = 0; e < EPT; ++e) {
+            const int r = rg + TPC * e;
+            if (r > j) ss = __builtin_fma(a[e], a[e], ss);
+            if (r == j) alpha = a[e];
+          }
+          ss = group_sum<TPC>(ss);
+          alpha = group_sum<TPC>(alpha);  // only the owner of row j holds a nonzero term
+          double tau = 0.0, beta = alpha, scal = 0.0;
+          if (ss != 0.0) {
+            beta = -copysign(sqrt(__builtin_fma(alpha, alpha, ss)), alpha);
+            tau = (beta - alpha) / beta;
+            scal = 1.0 / (alpha - beta);
+          }
+#pragma unroll
+          for (int e = 0; e < EPT; ++e) {
+            const int r = rg + TPC * e;
+            if (r == j) {
+              vbuf[buf][jj][r] = 1.0;
+              a[e] = beta;
+            } else if (r > j) {
+              vbuf[buf][jj][r] = a[e] * scal;
+              a[e] = 0.0;
+            }
+          }
+          if (rg == 0) taub[buf][jj] = tau;
+        }
+        wave_lds_sync();
+        if (c > j && c < qend) apply(vbuf[buf][jj], taub[buf][jj], j);
+      }
+    }
     __syncthreads();
-    if (c > j && c < n) {
-      const double tau = taub[buf];
-      double d = 0.0;
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const int r = rg + TPC * e;
-        if (r >= j && r < p) d = __builtin_fma(vbuf[buf][r], a[e], d);
-      }
-      for (int off = TPC / 2; off > 0; off >>= 1) d += shfl_xor_d(d, off);
-      const double tw = tau * d;
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const int r = rg + TPC * e;
-        if (r >= j && r < p) a[e] = __builtin_fma(-tw, vbuf[buf][r], a[e]);
-      }
+    if (c >= qend && c < n) {
+      for (int j = q; j < qend; ++j) apply(vbuf[buf][j - q], taub[buf][j - q], j);
     }
   }
   double* R = out + (int64_t)blockIdx.x * n * n;
@@ -112,15 +129,15 @@ hipError_t launch_qr_blocks(const double* in, int64_t ldin, int64_t p_total, int
   if (rows_per_block > kQrMaxRows || n > RCQR_MAX_N || n < 1) return hipErrorInvalidValue;
   const dim3 grid((unsigned)nblocks);
   if (n <= 8)
-    hipLaunchKernelGGL(qr_block_kernel<8>, grid, dim3(8 * 64), 0, s, in, ldin, p_total, rows_per_block, n, out);
+    hipLaunchKernelGGL((qr_block_kernel<8, 64>), grid, dim3(8 * 64), 0, s, in, ldin, p_total, rows_per_block, n, out);
   else if (n <= 16)
-    hipLaunchKernelGGL(qr_block_kernel<16>, grid, dim3(1024), 0, s, in, ldin, p_total, rows_per_block, n, out);
+    hipLaunchKernelGGL((qr_block_kernel<16, 16>), grid, dim3(16 * 16), 0, s, in, ldin, p_total, rows_per_block, n, out);
   else if (n <= 32)
-    hipLaunchKernelGGL(qr_block_kernel<32>, grid, dim3(1024), 0, s, in, ldin, p_total, rows_per_block, n, out);
+    hipLaunchKernelGGL((qr_block_kernel<32, 32>), grid, dim3(32 * 32), 0, s, in, ldin, p_total, rows_per_block, n, out);
   else if (n <= 64)
-    hipLaunchKernelGGL(qr_block_kernel<64>, grid, dim3(1024), 0, s, in, ldin, p_total, rows_per_block, n, out);
+    hipLaunchKernelGGL((qr_block_kernel<64, 16>), grid, dim3(64 * 16), 0, s, in, ldin, p_total, rows_per_block, n, out);
   else
-    hipLaunchKernelGGL(qr_block_kernel<128>, grid, dim3(1024), 0, s, in, ldin, p_total, rows_per_block, n, out);
+    hipLaunchKernelGGL((qr_block_kernel<128, 8>), grid, dim3(128 * 8), 0, s, in, ldin, p_total, rows_per_block, n, out);
   return hipGetLastError();
 }
 
@@ -154,22 +171,18 @@ __device__ __forceinline__ void put_packed(double* pk, int np, int n, int r, int
 // ------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void finalize_r0_kernel(const double* __restrict__ rin, int n, int np, int32_t* __restrict__ info,
                                                           double* __restrict__ r0, double* __restrict__ r0pk) {
-  __shared__ int bad;
-  if (threadIdx.x == 0) {
-    bad = 0;
-    for (int j = 0; j < n; ++j) {
-      const double d = rin[j * n + j];
-      if (!(d != 0.0) || !isfinite(d)) {
-        bad = j + 1;
-        break;
-      }
-    }
-    if (bad) {
-      info[0] = RCQR_E_RANK;
-      info[1] = bad;
-    }
+  __shared__ int bad;  // first failing column (1-based), or a value > n
+  if (threadIdx.x == 0) bad = n + 1;
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const double d = rin[j * n + j];
+    if (!(d != 0.0) || !isfinite(d)) atomicMin(&bad, j + 1);
   }
   __syncthreads();
+  if (threadIdx.x == 0 && bad <= n) {
+    info[0] = RCQR_E_RANK;
+    info[1] = bad;
+  }
   for (int i = threadIdx.x; i < np * np; i += blockDim.x) {
     const int r = i / np, c = i % np;
     double v = 0.0;
@@ -273,8 +286,91 @@ __global__ __launch_bounds__(256) void cholesky_kernel(const double* __restrict_
   }
 }
 
+// Cholesky for np <= 64 with short, rolled loops (a fully unrolled single-wave factorization
+// is tens of KB of straight-line code that runs once and is bound by instruction fetch).
+// G lives in LDS (row-major, upper triangle; the lower triangle is scratch).  Wave 0 factors:
+// step j divides row j by sqrt(G[j][j]) and lane c updates column c below row j,
+// G[i][c] -= R1[j][i] R1[j][c] for j < i <= c.  Then all four waves form R = R1 Rprev.
+template <int NP>
+__global__ __launch_bounds__(256) void cholesky_small_kernel(const double* __restrict__ gc, int n, const double* __restrict__ rprev,
+                                                             int32_t* __restrict__ info, double* __restrict__ g_out, double* __restrict__ r1,
+                                                             double* __restrict__ r1pk, double* __restrict__ r_out, int64_t ldr) {
+  __shared__ double G[NP * NP];
+  __shared__ double P[NP * NP];  // Rprev, zero-padded
+  __shared__ int fail;
+  if (info[0] != 0) return;
+  constexpr int NB = NP / 16;
+  const int t = threadIdx.x;
+  for (int idx = t; idx < NP * NP; idx += blockDim.x) {
+    const int i = idx / NP, c = idx % NP;
+    double v = 0.0, pv = 0.0;
+    if (i <= c && c < n) {
+      v = gc[upper_block_index(i / 16, c / 16, NB) * 256 + (i % 16) * 16 + (c % 16)];
+      pv = rprev[i * n + c];
+    }
+    G[idx] = v;
+    P[idx] = pv;
+    if (i < n && c < n) g_out[i * n + c] = v;
+  }
+  if (t == 0) fail = 0;
+  __syncthreads();
+  if (t < kWave) {
+    const int c = t;
+    for (int j = 0; j < n; ++j) {
+      const double d = G[j * NP + j];
+      if (!(d > 0.0)) {  // NaN fails too; uniform across the wave
+        if (c == 0) fail = j + 1;
+        break;
+      }
+      const double rjj = sqrt(d);
+      const double inv = 1.0 / rjj;
+      if (c > j && c < n) G[j * NP + c] *= inv;
+      if (c == j) G[j * NP + j] = rjj;
+      wave_lds_sync();
+      if (c > j && c < n) {
+        const double rjc = G[j * NP + c];
+        for (int i = j + 1; i <= c; ++i) G[i * NP + c] = __builtin_fma(-G[j * NP + i], rjc, G[i * NP + c]);
+      }
+      wave_lds_sync();
+    }
+  }
+  __syncthreads();
+  if (fail) {
+    if (t == 0) {
+      info[0] = RCQR_E_CHOL;
+      info[1] = fail;
+    }
+    return;
+  }
+  // R1, its packed padded form, and R = R1 Rprev: R[i][c] = sum_{l = i..c} R1[i][l] Rprev[l][c]
+  for (int idx = t; idx < NP * NP; idx += blockDim.x) {
+    const int i = idx / NP, c = idx % NP;
+    const double v = (i <= c && c < n) ? G[idx] : 0.0;
+    if (i < n && c < n) r1[i * n + c] = v;
+    if (c >= i) put_packed(r1pk, NP, n, i, c, v);
+    if (i < n && c < n) {
+      double acc = 0.0;
+      if (i <= c)
+        for (int l = i; l <= c; ++l) acc = __builtin_fma(G[i * NP + l], P[l * NP + c], acc);
+      r_out[(int64_t)i * ldr + c] = acc;
+    }
+  }
+}
+
 hipError_t launch_cholesky(const double* gcompact, int n, int np, const double* rprev, int32_t* info, double* g_out,
                            double* r1, double* r1pk, double* r_out, int64_t ldr, hipStream_t s) {
+  if (np == 16) {
+    hipLaunchKernelGGL(cholesky_small_kernel<16>, dim3(1), dim3(256), 0, s, gcompact, n, rprev, info, g_out, r1, r1pk, r_out, ldr);
+    return hipGetLastError();
+  }
+  if (np == 32) {
+    hipLaunchKernelGGL(cholesky_small_kernel<32>, dim3(1), dim3(256), 0, s, gcompact, n, rprev, info, g_out, r1, r1pk, r_out, ldr);
+    return hipGetLastError();
+  }
+  if (np == 64) {
+    hipLaunchKernelGGL(cholesky_small_kernel<64>, dim3(1), dim3(256), 0, s, gcompact, n, rprev, info, g_out, r1, r1pk, r_out, ldr);
+    return hipGetLastError();
+  }
   const size_t lds = (size_t)n * n * sizeof(double);
   static bool attr_set = false;  // G of 128 x 128 needs 128 KiB of dynamic LDS
   if (!attr_set) {

@@ -193,18 +193,31 @@ __global__ __launch_bounds__(kGramThreads, 1) void trsm_gram_kernel(const double
   for (int i = threadIdx.x; i < NBU * 256; i += kGramThreads) out[i] = gl[i];
 }
 
-template <int NP, bool APPLY_R1, bool FULL>
-__global__ __launch_bounds__(256) void final_kernel(const double* __restrict__ V, int64_t m, int n, int64_t ldv,
-                                                    const double* __restrict__ R0pk, const double* __restrict__ R1pk,
-                                                    const int32_t* __restrict__ info, double* __restrict__ Q, int64_t ldq) {
+// Persistent and phase-aligned: workgroup b takes tiles b*NW + w + k*gridDim.x*NW; in every
+// round all its waves solve with R0, meet at a barrier, then solve with R1.  The two packed
+// factors (16.6 KB each at 64 columns) do not fit the scalar data cache together, so keeping
+// the waves of a CU on the same factor at the same time keeps the coefficient stream hitting.
+template <int NP, bool APPLY_R1, bool FULL, int NW>
+__global__ __launch_bounds__(NW * kWave) void final_kernel(const double* __restrict__ V, int64_t m, int n, int64_t ldv,
+                                                          const double* __restrict__ R0pk, const double* __restrict__ R1pk,
+                                                          const int32_t* __restrict__ info, double* __restrict__ Q, int64_t ldq) {
   if (info[0] != 0) return;
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= m) return;
-  double x[NP];
-  load_row<NP, FULL>(x, V, row, m, n, ldv);
-  rowsolve<NP>(x, R0pk);
-  if constexpr (APPLY_R1) rowsolve<NP>(x, R1pk);
-  store_row<NP, FULL>(x, Q, row, n, ldq);
+  const int wave = threadIdx.x / kWave, lane = lane_id();
+  const int64_t ntiles = (m + kWave - 1) / kWave;
+  const int64_t per_round = (int64_t)gridDim.x * NW;
+  const int64_t rounds = (ntiles + per_round - 1) / per_round;
+  for (int64_t r = 0; r < rounds; ++r) {
+    const int64_t row = (r * per_round + (int64_t)blockIdx.x * NW + wave) * kWave + lane;
+    double x[NP];
+    load_row<NP, FULL>(x, V, row, m, n, ldv);
+    rowsolve<NP>(x, R0pk);
+    if constexpr (APPLY_R1) {
+      __syncthreads();
+      rowsolve<NP>(x, R1pk);
+    }
+    if (row < m) store_row<NP, FULL>(x, Q, row, n, ldq);
+    if constexpr (APPLY_R1) __syncthreads();
+  }
 }
 
 static bool full_rows(int np, int n, const void* a, int64_t lda, const void* b, int64_t ldb) {
@@ -232,24 +245,40 @@ hipError_t launch_trsm_gram(int np, const double* V, int64_t m, int n, int64_t l
   return hipGetLastError();
 }
 
+static int final_grid() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      cus = 256;
+  }
+  return cus;
+}
+
 hipError_t launch_final(int np, bool apply_r1, const double* V, int64_t m, int n, int64_t ldv, const double* r0pk,
                         const double* r1pk, const int32_t* info, double* Q, int64_t ldq, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((m + 255) / 256)), block(256);
   const bool full = full_rows(np, n, V, ldv, Q, ldq);
-#define RCQR_FINAL(NPV)                                                                                                    \
-  if (apply_r1 && full)                                                                                                    \
-    hipLaunchKernelGGL((final_kernel<NPV, true, true>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq);      \
-  else if (apply_r1)                                                                                                       \
-    hipLaunchKernelGGL((final_kernel<NPV, true, false>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq);     \
-  else if (full)                                                                                                           \
-    hipLaunchKernelGGL((final_kernel<NPV, false, true>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq);     \
-  else                                                                                                                     \
-    hipLaunchKernelGGL((final_kernel<NPV, false, false>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq);
+  // waves per workgroup = waves that fit one CU at this kernel's register use (one workgroup per CU)
+#define RCQR_FINAL(NPV, NWV)                                                                                                    \
+  {                                                                                                                             \
+    const int64_t tiles = (m + kWave - 1) / kWave;                                                                              \
+    int64_t g = (tiles + NWV - 1) / NWV;                                                                                        \
+    if (g > final_grid()) g = final_grid();                                                                                     \
+    const dim3 grid((unsigned)g), block(NWV * kWave);                                                                           \
+    if (apply_r1 && full)                                                                                                       \
+      hipLaunchKernelGGL((final_kernel<NPV, true, true, NWV>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq);     \
+    else if (apply_r1)                                                                                                          \
+      hipLaunchKernelGGL((final_kernel<NPV, true, false, NWV>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq);    \
+    else if (full)                                                                                                              \
+      hipLaunchKernelGGL((final_kernel<NPV, false, true, NWV>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq);    \
+    else                                                                                                                        \
+      hipLaunchKernelGGL((final_kernel<NPV, false, false, NWV>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq);   \
+  }
   switch (np) {
-    case 16: RCQR_FINAL(16) break;
-    case 32: RCQR_FINAL(32) break;
-    case 64: RCQR_FINAL(64) break;
+    case 16: RCQR_FINAL(16, 16) break;
+    case 32: RCQR_FINAL(32, 16) break;
+    case 64: RCQR_FINAL(64, 12) break;
     default: return hipErrorInvalidValue;
   }
 #undef RCQR_FINAL
