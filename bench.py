@@ -10,9 +10,10 @@ kappa(V) = 1e12, CountSketch s1 = 8192, Gaussian s2 = 256, seed 1.
 
 Prints one JSON line: QR/s (value), algorithmic GB/s (32 m n bytes per factorization), the
 roofline of the dominant kernel (HIP-event durations measured inside the timed region), the
-accuracy of the result, and the CPU oracle timed on a bounded sample of the same workload.
+accuracy of the result, cholQR2 and shifted CholeskyQR3 run on the same V and GPU (after the
+timed region), and the CPU oracle timed on a bounded sample of the same workload.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-comparators]
 """
 
 import argparse
@@ -69,6 +70,32 @@ def gram_accurate(Q, chunk=4096):
     return parts[0]
 
 
+def comparators(plan, V, Q, R, eye, tgt, steps):
+    """cholQR2 (Algorithm 4) and shifted CholeskyQR3 on the same V and GPU (Section 6.3's comparison)."""
+    import torch
+
+    out = {}
+    stream = plan.stream
+    for name, fn in (("cholqr2", plan.cholqr2), ("scholqr3", plan.scholqr3)):
+        fn(V, Q, R, check=False)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(steps):
+            fn(V, Q, R, check=False)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        st, col = plan.info()
+        rec = {"ms_per_qr": round(ev0.elapsed_time(ev1) / steps, 4), "status": st, "failed_column": col}
+        if st == 0:
+            rec["orth_error"] = torch.linalg.norm(eye - gram_accurate(Q)).item()
+            rec["residual"] = (torch.linalg.norm(V - Q @ R) / torch.linalg.norm(V)).item()
+            rec["within_target"] = bool(rec["orth_error"] <= tgt and rec["residual"] <= tgt)
+        else:
+            rec["within_target"] = False
+        out[name] = rec
+    return out
+
+
 def cpu_baseline(wl, sample_rows):
     """The oracle as it stands, single-threaded, on a row-scaled sample of the workload."""
     from threadpoolctl import threadpool_limits
@@ -97,6 +124,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-comparators", action="store_true", help="skip timing cholQR2 and sCholQR3 on the same V")
+    ap.add_argument("--comparator-steps", type=int, default=5)
     ap.add_argument("--cpu-sample-rows", type=int, default=100_000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device-to-device copy of V's size (HBM counter calibration)")
@@ -192,6 +221,8 @@ def main():
         "orth_error": orth, "residual": res, "target_10nu": tgt, "within_target": bool(orth <= tgt and res <= tgt),
         "roofline": roofline,
     }
+    if not args.no_comparators:
+        out["comparators"] = comparators(plan, V, Q, R, eye, tgt, args.comparator_steps)
     if not args.no_cpu_baseline:
         log(f"bench: cpu baseline on {args.cpu_sample_rows} rows")
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_rows)

@@ -92,6 +92,17 @@ rcqr_status_t rcqr_factor(rcqr_plan_t plan, const double* d_V, int64_t ldv, doub
 rcqr_status_t rcqr_cholqr2(rcqr_plan_t plan, const double* d_V, int64_t ldv, double* d_Q, int64_t ldq,
                            double* d_R, int64_t ldr);
 
+/*
+ * Shifted CholeskyQR3, the other comparator of Section 6 (cited in Section 1 as stable up to
+ * kappa(V) of about u^{-1}): Ra = chol(V^T V + s I) with s = 11 (m n + n (n + 1)) u ||V||_F^2,
+ * u = 2^-52; Qa = V Ra^{-1}; then cholQR2 of Qa (Algorithm 4); R = Rc Rb Ra.  Qa is stored in
+ * d_Q (so V is read twice and Q written twice); d_Q may alias d_V with ldq == ldv.
+ * Same arguments, errors and stream semantics as rcqr_factor; a failing Cholesky reports
+ * RCQR_E_CHOL through rcqr_info.
+ */
+rcqr_status_t rcqr_scholqr3(rcqr_plan_t plan, const double* d_V, int64_t ldv, double* d_Q, int64_t ldq,
+                            double* d_R, int64_t ldr);
+
 /* Wait for the plan's stream and report the last factorization: *status is an rcqr_status_t
  * (RCQR_OK, RCQR_E_RANK or RCQR_E_CHOL), *column the 1-based failing column or 0. */
 rcqr_status_t rcqr_info(rcqr_plan_t plan, int32_t* status, int32_t* column);

@@ -30,6 +30,7 @@ _SIGNATURES = {
     "rcqr_plan": (_c_i32, [ctypes.POINTER(_c_p), _c_i64, _c_i64, _c_i64, _c_i64, _c_u64, _c_u32, _c_p, ctypes.c_size_t, _c_p]),
     "rcqr_factor": (_c_i32, [_c_p, _c_p, _c_i64, _c_p, _c_i64, _c_p, _c_i64]),
     "rcqr_cholqr2": (_c_i32, [_c_p, _c_p, _c_i64, _c_p, _c_i64, _c_p, _c_i64]),
+    "rcqr_scholqr3": (_c_i32, [_c_p, _c_p, _c_i64, _c_p, _c_i64, _c_p, _c_i64]),
     "rcqr_info": (_c_i32, [_c_p, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32)]),
     "rcqr_destroy": (_c_i32, [_c_p]),
     "rcqr_status_string": (ctypes.c_char_p, [_c_i32]),
@@ -145,23 +146,25 @@ class Plan:
         _check_matrix(R, self.n, self.n, "R")
         return Q, R
 
+    def _call(self, name, V, Q, R, check):
+        Q, R = self._outputs(V, Q, R)
+        _check(getattr(lib(), name)(self._h, ctypes.c_void_p(V.data_ptr()), V.stride(0), ctypes.c_void_p(Q.data_ptr()),
+                                    Q.stride(0), ctypes.c_void_p(R.data_ptr()), R.stride(0)), name)
+        if check:
+            self.raise_on_failure(name)
+        return Q, R
+
     def factor(self, V, Q=None, R=None, check=True):
         """Algorithm 3 on V; returns (Q, R).  With check=True waits and raises on RANK/CHOL."""
-        Q, R = self._outputs(V, Q, R)
-        _check(lib().rcqr_factor(self._h, ctypes.c_void_p(V.data_ptr()), V.stride(0), ctypes.c_void_p(Q.data_ptr()),
-                                 Q.stride(0), ctypes.c_void_p(R.data_ptr()), R.stride(0)), "rcqr_factor")
-        if check:
-            self.raise_on_failure("rcqr_factor")
-        return Q, R
+        return self._call("rcqr_factor", V, Q, R, check)
 
     def cholqr2(self, V, Q=None, R=None, check=True):
         """Algorithm 4 (cholQR2) on V with this plan's workspace; returns (Q, R)."""
-        Q, R = self._outputs(V, Q, R)
-        _check(lib().rcqr_cholqr2(self._h, ctypes.c_void_p(V.data_ptr()), V.stride(0), ctypes.c_void_p(Q.data_ptr()),
-                                  Q.stride(0), ctypes.c_void_p(R.data_ptr()), R.stride(0)), "rcqr_cholqr2")
-        if check:
-            self.raise_on_failure("rcqr_cholqr2")
-        return Q, R
+        return self._call("rcqr_cholqr2", V, Q, R, check)
+
+    def scholqr3(self, V, Q=None, R=None, check=True):
+        """Shifted CholeskyQR3 on V with this plan's workspace; returns (Q, R)."""
+        return self._call("rcqr_scholqr3", V, Q, R, check)
 
     def info(self):
         st, col = _c_i32(), _c_i32()
@@ -229,5 +232,14 @@ def cholqr2(V, check=True):
     m, n = V.shape
     with Plan(m, n, max(n, 16), n, 0, device=V.device) as p:
         Q, R = p.cholqr2(V, check=check)
+        torch.cuda.current_stream(V.device).synchronize()
+        return Q, R
+
+
+def scholqr3(V, check=True):
+    """One-shot shifted CholeskyQR3 on the GPU; returns (Q, R)."""
+    m, n = V.shape
+    with Plan(m, n, max(n, 16), n, 0, device=V.device) as p:
+        Q, R = p.scholqr3(V, check=check)
         torch.cuda.current_stream(V.device).synchronize()
         return Q, R

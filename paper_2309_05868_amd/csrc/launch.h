@@ -52,8 +52,9 @@ hipError_t launch_finalize_r0(const double* rin, int n, int np, int32_t* info, d
 // Cholesky of the Gram matrix held as compact upper 16x16 blocks; writes G (n x n, upper,
 // lower zero), R1 and its packed padded form, and R = R1 * Rprev into the caller's R
 // (ld ldr).  A non-positive pivot sets status CHOL.
-hipError_t launch_cholesky(const double* gcompact, int n, int np, const double* rprev, int32_t* info, double* g_out,
-                           double* r1, double* r1pk, double* r_out, int64_t ldr, hipStream_t s);
+// shift_coef != 0 factors G + shift_coef * trace(G) * I instead of G.
+hipError_t launch_cholesky(const double* gcompact, int n, int np, const double* rprev, double shift_coef, int32_t* info,
+                           double* g_out, double* r1, double* r1pk, double* r_out, int64_t ldr, hipStream_t s);
 // Identity (n x n) into r0 and its packed padded form into r0pk.
 hipError_t launch_identity_factor(int n, int np, double* r0, double* r0pk, hipStream_t s);
 

@@ -1,5 +1,6 @@
 // Host side of the rcqr C ABI: argument checks, workspace layout, and the order of the kernel
-// launches of Algorithm 3 (rand_cholQR) and Algorithm 4 (cholQR2) on the plan's stream.
+// launches of Algorithm 3 (rand_cholQR), Algorithm 4 (cholQR2) and shifted CholeskyQR3 on the
+// plan's stream.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -29,7 +30,7 @@ int padded_cols(int64_t n) {
 
 struct Layout {
   size_t info, w1, csparts, codes, counts, offsets, hist, entries, wpart, w, qra, qrb, r0, r0pk, gpart, gc, g, r1, r1pk,
-      ra, rapk, rtmp, total;
+      ra, rapk, rtmp, rtmp2, total;
 };
 
 struct Shape {
@@ -107,6 +108,7 @@ Layout make_layout(const Shape& sh) {
   L.ra = take(n * n * 8);
   L.rapk = take(pk);
   L.rtmp = take(n * n * 8);
+  L.rtmp2 = take(n * n * 8);
   L.total = off;
   return L;
 }
@@ -211,6 +213,18 @@ static rcqr_status_t run_final(rcqr_plan_t p, const double* V, int64_t ldv, cons
     RCQR_TRY(launch_final(sh.np, true, V, sh.m, (int)sh.n, ldv, r0pk, r1pk, info, Q, ldq, p->stream));
   } else {
     RCQR_TRY(launch_solve128(Q, sh.m, (int)sh.n, ldq, r1pk, info, Q, ldq, p->stream));
+  }
+  return RCQR_OK;
+}
+
+// X R^{-1} written to Q (one row-wise substitution; Q may alias X).
+static rcqr_status_t run_solve(rcqr_plan_t p, const double* X, int64_t ldx, const double* rpk, double* Q, int64_t ldq) {
+  const Shape& sh = p->sh;
+  const int32_t* info = p->at<int32_t>(p->L.info);
+  if (sh.np <= 64) {
+    RCQR_TRY(launch_final(sh.np, false, X, sh.m, (int)sh.n, ldx, rpk, rpk, info, Q, ldq, p->stream));
+  } else {
+    RCQR_TRY(launch_solve128(X, sh.m, (int)sh.n, ldx, rpk, info, Q, ldq, p->stream));
   }
   return RCQR_OK;
 }
@@ -360,8 +374,8 @@ rcqr_status_t rcqr_factor(rcqr_plan_t p, const double* V, int64_t ldv, double* Q
   if (run_gram(p, V, ldv, p->at<double>(L.r0pk), Q, ldq) != RCQR_OK) return RCQR_E_HIP;
   if (mark(p, 4) != RCQR_OK) return RCQR_E_HIP;
   // Algorithm 2, step 2 and Algorithm 3, step 3: R1 = chol(G), R = R1 R0
-  RCQR_TRY(launch_cholesky(p->at<double>(L.gc), n, sh.np, p->at<double>(L.r0), info, p->at<double>(L.g), p->at<double>(L.r1),
-                           p->at<double>(L.r1pk), R, ldr, s));
+  RCQR_TRY(launch_cholesky(p->at<double>(L.gc), n, sh.np, p->at<double>(L.r0), 0.0, info, p->at<double>(L.g),
+                           p->at<double>(L.r1), p->at<double>(L.r1pk), R, ldr, s));
   if (mark(p, 5) != RCQR_OK) return RCQR_E_HIP;
   // Algorithm 2, step 3 on Q0: Q = Q0 R1^{-1}
   if (run_final(p, V, ldv, p->at<double>(L.r0pk), p->at<double>(L.r1pk), Q, ldq) != RCQR_OK) return RCQR_E_HIP;
@@ -382,13 +396,43 @@ rcqr_status_t rcqr_cholqr2(rcqr_plan_t p, const double* V, int64_t ldv, double* 
   // first cholQR: G = V^T V (R0 := I), Ra = chol(G)
   RCQR_TRY(launch_identity_factor(n, sh.np, p->at<double>(L.r0), p->at<double>(L.r0pk), s));
   if (run_gram(p, V, ldv, p->at<double>(L.r0pk), Q, ldq) != RCQR_OK) return RCQR_E_HIP;
-  RCQR_TRY(launch_cholesky(p->at<double>(L.gc), n, sh.np, p->at<double>(L.r0), info, p->at<double>(L.g), p->at<double>(L.ra),
-                           p->at<double>(L.rapk), p->at<double>(L.rtmp), n, s));
+  RCQR_TRY(launch_cholesky(p->at<double>(L.gc), n, sh.np, p->at<double>(L.r0), 0.0, info, p->at<double>(L.g),
+                           p->at<double>(L.ra), p->at<double>(L.rapk), p->at<double>(L.rtmp), n, s));
   // second cholQR on Q0 = V Ra^{-1}: Rb = chol(Q0^T Q0), R = Rb Ra
   if (run_gram(p, V, ldv, p->at<double>(L.rapk), Q, ldq) != RCQR_OK) return RCQR_E_HIP;
-  RCQR_TRY(launch_cholesky(p->at<double>(L.gc), n, sh.np, p->at<double>(L.rtmp), info, p->at<double>(L.g), p->at<double>(L.r1),
-                           p->at<double>(L.r1pk), R, ldr, s));
+  RCQR_TRY(launch_cholesky(p->at<double>(L.gc), n, sh.np, p->at<double>(L.rtmp), 0.0, info, p->at<double>(L.g),
+                           p->at<double>(L.r1), p->at<double>(L.r1pk), R, ldr, s));
   if (run_final(p, V, ldv, p->at<double>(L.rapk), p->at<double>(L.r1pk), Q, ldq) != RCQR_OK) return RCQR_E_HIP;
+  return RCQR_OK;
+}
+
+rcqr_status_t rcqr_scholqr3(rcqr_plan_t p, const double* V, int64_t ldv, double* Q, int64_t ldq, double* R, int64_t ldr) {
+  const rcqr_status_t st = check_io(p, V, ldv, Q, ldq, R, ldr);
+  if (st != RCQR_OK) return st;
+  const Shape& sh = p->sh;
+  const Layout& L = p->L;
+  const int n = (int)sh.n;
+  hipStream_t s = p->stream;
+  int32_t* info = p->at<int32_t>(L.info);
+  double* gc = p->at<double>(L.gc);
+  double* g = p->at<double>(L.g);
+  const double u = std::ldexp(1.0, -52);
+  const double coef = 11.0 * ((double)sh.m * (double)sh.n + (double)sh.n * (double)(sh.n + 1)) * u;
+  RCQR_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(info), 16, 0u, s));
+  RCQR_TRY(launch_identity_factor(n, sh.np, p->at<double>(L.r0), p->at<double>(L.r0pk), s));
+  // shifted cholQR: Ra = chol(V^T V + s I), s = coef ||V||_F^2; Qa = V Ra^{-1} stored in Q
+  if (run_gram(p, V, ldv, p->at<double>(L.r0pk), Q, ldq) != RCQR_OK) return RCQR_E_HIP;
+  RCQR_TRY(launch_cholesky(gc, n, sh.np, p->at<double>(L.r0), coef, info, g, p->at<double>(L.ra), p->at<double>(L.rapk),
+                           p->at<double>(L.rtmp), n, s));
+  if (run_solve(p, V, ldv, p->at<double>(L.rapk), Q, ldq) != RCQR_OK) return RCQR_E_HIP;
+  // cholQR2 of Qa in place: Rb = chol(Qa^T Qa), Rc = chol((Qa Rb^{-1})^T (Qa Rb^{-1})), R = Rc Rb Ra
+  if (run_gram(p, Q, ldq, p->at<double>(L.r0pk), Q, ldq) != RCQR_OK) return RCQR_E_HIP;
+  RCQR_TRY(launch_cholesky(gc, n, sh.np, p->at<double>(L.rtmp), 0.0, info, g, p->at<double>(L.r1), p->at<double>(L.r1pk),
+                           p->at<double>(L.rtmp2), n, s));
+  if (run_gram(p, Q, ldq, p->at<double>(L.r1pk), Q, ldq) != RCQR_OK) return RCQR_E_HIP;
+  RCQR_TRY(launch_cholesky(gc, n, sh.np, p->at<double>(L.rtmp2), 0.0, info, g, p->at<double>(L.ra), p->at<double>(L.rapk), R,
+                           ldr, s));
+  if (run_final(p, Q, ldq, p->at<double>(L.r1pk), p->at<double>(L.rapk), Q, ldq) != RCQR_OK) return RCQR_E_HIP;
   return RCQR_OK;
 }
 

@@ -7,7 +7,9 @@
 //  finalize_r0       positive diagonal (rows of R scaled by the sign of their diagonal, which
 //                    makes R0 the unique R of W), rank check, and the packed padded copy the
 //                    streaming passes read (upper triangle row by row, reciprocal diagonal).
-//  cholesky_kernel   R1 = chol(G) (Algorithm 2, step 2) and R = R1 R0 (Algorithm 3, step 3).
+//  cholesky_kernel   R1 = chol(G) (Algorithm 2, step 2) and R = R1 R0 (Algorithm 3, step 3);
+//                    with a nonzero shift coefficient c, chol(G + c trace(G) I), the first step
+//                    of shifted CholeskyQR3 (trace(G) = ||V||_F^2 when G = V^T V).
 #include "device_common.h"
 #include "launch.h"
 
@@ -222,11 +224,20 @@ __device__ __forceinline__ int upper_block_index(int a, int b, int nb) {
   return a * nb - a * (a - 1) / 2 + (b - a);
 }
 
+// trace of an LDS matrix with row stride ld, summed in index order
+static __device__ double diag_sum(const double* a, int n, int ld) {
+  double tr = 0.0;
+  for (int i = 0; i < n; ++i) tr += a[i * ld + i];
+  return tr;
+}
+
 __global__ __launch_bounds__(256) void cholesky_kernel(const double* __restrict__ gc, int n, int np, const double* __restrict__ rprev,
-                                                       int32_t* __restrict__ info, double* __restrict__ g_out, double* __restrict__ r1,
-                                                       double* __restrict__ r1pk, double* __restrict__ r_out, int64_t ldr) {
+                                                       double shift_coef, int32_t* __restrict__ info, double* __restrict__ g_out,
+                                                       double* __restrict__ r1, double* __restrict__ r1pk, double* __restrict__ r_out,
+                                                       int64_t ldr) {
   extern __shared__ double g[];  // n x n
   __shared__ int fail;
+  __shared__ double shift;
   if (info[0] != 0) return;
   const int nb = np / 16;
   for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
@@ -241,6 +252,12 @@ __global__ __launch_bounds__(256) void cholesky_kernel(const double* __restrict_
   }
   if (threadIdx.x == 0) fail = 0;
   __syncthreads();
+  if (shift_coef != 0.0) {
+    if (threadIdx.x == 0) shift = shift_coef * diag_sum(g, n, n);
+    __syncthreads();
+    if (threadIdx.x < n) g[threadIdx.x * n + threadIdx.x] += shift;
+    __syncthreads();
+  }
   for (int j = 0; j < n; ++j) {
     const double d = g[j * n + j];
     if (!(d > 0.0)) {  // NaN fails too
@@ -293,11 +310,13 @@ __global__ __launch_bounds__(256) void cholesky_kernel(const double* __restrict_
 // G[i][c] -= R1[j][i] R1[j][c] for j < i <= c.  Then all four waves form R = R1 Rprev.
 template <int NP>
 __global__ __launch_bounds__(256) void cholesky_small_kernel(const double* __restrict__ gc, int n, const double* __restrict__ rprev,
-                                                             int32_t* __restrict__ info, double* __restrict__ g_out, double* __restrict__ r1,
-                                                             double* __restrict__ r1pk, double* __restrict__ r_out, int64_t ldr) {
+                                                             double shift_coef, int32_t* __restrict__ info, double* __restrict__ g_out,
+                                                             double* __restrict__ r1, double* __restrict__ r1pk, double* __restrict__ r_out,
+                                                             int64_t ldr) {
   __shared__ double G[NP * NP];
   __shared__ double P[NP * NP];  // Rprev, zero-padded
   __shared__ int fail;
+  __shared__ double shift;
   if (info[0] != 0) return;
   constexpr int NB = NP / 16;
   const int t = threadIdx.x;
@@ -314,6 +333,12 @@ __global__ __launch_bounds__(256) void cholesky_small_kernel(const double* __res
   }
   if (t == 0) fail = 0;
   __syncthreads();
+  if (shift_coef != 0.0) {
+    if (t == 0) shift = shift_coef * diag_sum(G, n, NP);
+    __syncthreads();
+    if (t < n) G[t * NP + t] += shift;
+    __syncthreads();
+  }
   if (t < kWave) {
     const int c = t;
     for (int j = 0; j < n; ++j) {
@@ -357,18 +382,18 @@ __global__ __launch_bounds__(256) void cholesky_small_kernel(const double* __res
   }
 }
 
-hipError_t launch_cholesky(const double* gcompact, int n, int np, const double* rprev, int32_t* info, double* g_out,
-                           double* r1, double* r1pk, double* r_out, int64_t ldr, hipStream_t s) {
+hipError_t launch_cholesky(const double* gcompact, int n, int np, const double* rprev, double shift_coef, int32_t* info,
+                           double* g_out, double* r1, double* r1pk, double* r_out, int64_t ldr, hipStream_t s) {
   if (np == 16) {
-    hipLaunchKernelGGL(cholesky_small_kernel<16>, dim3(1), dim3(256), 0, s, gcompact, n, rprev, info, g_out, r1, r1pk, r_out, ldr);
+    hipLaunchKernelGGL(cholesky_small_kernel<16>, dim3(1), dim3(256), 0, s, gcompact, n, rprev, shift_coef, info, g_out, r1, r1pk, r_out, ldr);
     return hipGetLastError();
   }
   if (np == 32) {
-    hipLaunchKernelGGL(cholesky_small_kernel<32>, dim3(1), dim3(256), 0, s, gcompact, n, rprev, info, g_out, r1, r1pk, r_out, ldr);
+    hipLaunchKernelGGL(cholesky_small_kernel<32>, dim3(1), dim3(256), 0, s, gcompact, n, rprev, shift_coef, info, g_out, r1, r1pk, r_out, ldr);
     return hipGetLastError();
   }
   if (np == 64) {
-    hipLaunchKernelGGL(cholesky_small_kernel<64>, dim3(1), dim3(256), 0, s, gcompact, n, rprev, info, g_out, r1, r1pk, r_out, ldr);
+    hipLaunchKernelGGL(cholesky_small_kernel<64>, dim3(1), dim3(256), 0, s, gcompact, n, rprev, shift_coef, info, g_out, r1, r1pk, r_out, ldr);
     return hipGetLastError();
   }
   const size_t lds = (size_t)n * n * sizeof(double);
@@ -379,7 +404,7 @@ hipError_t launch_cholesky(const double* gcompact, int n, int np, const double* 
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(256), lds, s, gcompact, n, np, rprev, info, g_out, r1, r1pk, r_out, ldr);
+  hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(256), lds, s, gcompact, n, np, rprev, shift_coef, info, g_out, r1, r1pk, r_out, ldr);
   return hipGetLastError();
 }
 

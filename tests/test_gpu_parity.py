@@ -19,7 +19,7 @@ import synth
 from oracle import sketch as osk
 from oracle.countsketch import apply_countsketch
 from oracle.dense import householder_r
-from oracle.rand_cholqr import U_PAPER, rand_cholqr as oracle_rand_cholqr
+from oracle.rand_cholqr import U_PAPER, rand_cholqr as oracle_rand_cholqr, shifted_cholqr3 as oracle_scholqr3
 
 pytestmark = pytest.mark.gpu
 
@@ -210,3 +210,42 @@ def test_cholqr2_comparator():
         # rand_cholQR on the same plan still succeeds
         Q, R = p.factor(dev(hard))
         assert np.linalg.norm(np.eye(n) - host(Q).T @ host(Q)) <= tgt
+
+
+@pytest.mark.parametrize("n,s1,s2,k_mid", [(16, 512, 64, 1e10), (64, 8192, 256, 1e9), (100, 20_000, 400, 1e8)])
+def test_scholqr3_comparator(n, s1, s2, k_mid):
+    m = 20_000 + 37
+    tgt = 10 * n * U_PAPER
+    with rc.Plan(m, n, s1, s2, seed=50) as p:
+        # moderate kappa: R against the oracle's shifted CholeskyQR3 and LAPACK
+        say(f"scholqr3: n={n} kappa=1e5")
+        V = synth.make_V(m, n, 1e5, seed=50 + n)
+        Q, R = p.scholqr3(dev(V))
+        Qo, Ro, st, _ = oracle_scholqr3(V)
+        assert st == 0
+        Q, R = host(Q), host(R)
+        assert rel(R, Ro) <= 1e-10 and rel(R, lapack_r(V)) <= 1e-10
+        assert np.linalg.norm(np.eye(n) - Q.T @ Q) <= tgt
+        assert np.all(np.diag(R) > 0) and np.all(np.tril(R, -1) == 0)
+        # in place (Q aliases V): bitwise the same as out of place
+        Vi = dev(V)
+        Qi, Ri = p.scholqr3(Vi, Q=Vi)
+        np.testing.assert_array_equal(host(Qi), Q)
+        np.testing.assert_array_equal(host(Ri), R)
+        # inside its range (Section 6.3: up to about 1e11)
+        say(f"scholqr3: n={n} kappa={k_mid:.0e}")
+        Vm = synth.make_V(m, n, k_mid, seed=60 + n)
+        Q, R = p.scholqr3(dev(Vm))
+        Q, R = host(Q), host(R)
+        assert np.linalg.norm(np.eye(n) - Q.T @ Q) <= tgt
+        assert np.linalg.norm(Vm - Q @ R) / np.linalg.norm(Vm) <= tgt
+        # past it: breaks down or misses the target, while rand_cholQR on the same plan does not
+        say(f"scholqr3: n={n} kappa=1e15")
+        Vw = synth.make_V(m, n, 1e15, seed=70 + n)
+        Q, R = p.scholqr3(dev(Vw), check=False)
+        st, _ = p.info()
+        assert st == rc.E_CHOL or np.linalg.norm(np.eye(n) - host(Q).T @ host(Q)) > tgt
+        Q, R = p.factor(dev(Vw))
+        Q = host(Q)
+        assert np.linalg.norm(np.eye(n) - Q.T @ Q) <= tgt
+
