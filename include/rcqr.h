@@ -63,7 +63,29 @@ typedef enum {
 /* Largest number of columns the kernels support. */
 #define RCQR_MAX_N 128
 
-/* Bytes of device workspace a plan of this shape needs (0 if the shape is invalid). */
+/*
+ * Plan flags (bitwise OR; 0 = the method as written, everything in FP64).
+ *
+ * RCQR_FLAG_SKETCH_FP32: the preconditioner is computed in single precision: W1 = S1 V accumulates
+ *   V's entries rounded to FP32, W = S2 W1 runs on the FP32 matrix cores (S2 entries are the FP64
+ *   contract values rounded to FP32) with FP32 accumulation, and the Householder R0 is computed
+ *   in FP32 and promoted to FP64.  Everything after R0 (Q0 = V R0^{-1}, the Gram matrix, the
+ *   Cholesky, the final pass) stays FP64.  Only R0's quality as a preconditioner changes
+ *   (Section 5 needs S2 S1 to be an embedding and R0 backward stable): the rounding error of the
+ *   sketch is about u32 kappa(V) relative to its smallest singular value, so kappa(Q0) grows like
+ *   u32 kappa(V) once kappa(V) exceeds about 1/u32 = 1.7e7; combine with RCQR_FLAG_REORTH there.
+ * RCQR_FLAG_GEMM_BF16 (requires RCQR_FLAG_SKETCH_FP32): the Gaussian product's operands are
+ *   rounded to BF16 (FP32 accumulation), a relative perturbation of about 2^-9 of W1 and S2.
+ * RCQR_FLAG_REORTH: one more Cholesky QR after the first: Rc = R1 R0, Q1 = V Rc^{-1} by row-wise
+ *   substitution, R2 = chol(Q1^T Q1), Q = Q1 R2^{-1}, R = R2 Rc (one more read of V).  Needed when
+ *   kappa(Q0) is far from 1, that is with the single-precision sketch at large kappa(V).
+ */
+#define RCQR_FLAG_SKETCH_FP32 1u
+#define RCQR_FLAG_GEMM_BF16 2u
+#define RCQR_FLAG_REORTH 4u
+
+/* Bytes of device workspace a plan of this shape needs (0 if the shape or the flags are
+ * invalid; the flags do not change the size). */
 size_t rcqr_workspace_bytes(int64_t m, int64_t n, int64_t s1, int64_t s2, uint32_t flags);
 
 /*
@@ -71,7 +93,9 @@ size_t rcqr_workspace_bytes(int64_t m, int64_t n, int64_t s1, int64_t s2, uint32
  * (Algorithm 1's S1 of s1 x m and S2 of s2 x s1).  Requires 1 <= n <= 128, n <= m,
  * n <= s2 <= s1, s1 < 2^31, m < 2^31; s1 > m is accepted (the sketch is then not
  * compressive but still a CountSketch).  `stream` is a hipStream_t (NULL = default stream).
- * The workspace must stay valid until rcqr_destroy().  flags: 0.
+ * The workspace must stay valid until rcqr_destroy().  flags: RCQR_FLAG_* above (unknown bits,
+ * or RCQR_FLAG_GEMM_BF16 without RCQR_FLAG_SKETCH_FP32, give RCQR_E_INVALID); they apply to
+ * rcqr_factor only.
  */
 rcqr_status_t rcqr_plan(rcqr_plan_t* plan, int64_t m, int64_t n, int64_t s1, int64_t s2, uint64_t seed,
                         uint32_t flags, void* d_workspace, size_t workspace_bytes, void* stream);
@@ -122,7 +146,8 @@ const char* rcqr_status_string(int32_t status);
  * count through *count; rcqr_phase_name(i) names phase i.
  * Phases: 0 countsketch (sketch generation and W1 = S1 V), 1 gaussian (W = S2 W1),
  * 2 householder (R0), 3 trsm_gram (Q0 = V R0^{-1}, partial G), 4 cholesky (G, R1, R = R1 R0),
- * 5 final (Q = Q0 R1^{-1}, recomputing Q0).
+ * 5 reorth (the second Gram pass and Cholesky of RCQR_FLAG_REORTH; empty otherwise),
+ * 6 final (Q = Q0 R1^{-1}, recomputing Q0).
  */
 rcqr_status_t rcqr_set_timing(rcqr_plan_t plan, int32_t steps);
 rcqr_status_t rcqr_phase_times(rcqr_plan_t plan, float* ms, int32_t max, int32_t* count);
@@ -142,7 +167,8 @@ rcqr_status_t rcqr_gaussian_block(rcqr_plan_t plan, int64_t j0, int64_t nj, int6
 
 /* Copy the intermediates of the last rcqr_factor call from the workspace (device to device):
  * W1 (s1 x n), W (s2 x n), R0 (n x n), G (n x n, upper triangle; lower set to zero),
- * R1 (n x n).  Any pointer may be NULL. */
+ * R1 (n x n).  Any pointer may be NULL.  With RCQR_FLAG_SKETCH_FP32, W1 and W are the FP32
+ * values widened to FP64; with RCQR_FLAG_REORTH, G and R1 are those of the second pass. */
 rcqr_status_t rcqr_intermediates(rcqr_plan_t plan, double* d_W1, double* d_W, double* d_R0, double* d_G,
                                  double* d_R1);
 

@@ -20,6 +20,8 @@ HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "rcqr.h")
 
 OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_HIP, E_RANK, E_CHOL = range(7)
 MAX_N = 128  # largest number of columns the kernels accept
+# plan flags (include/rcqr.h): single-precision sketch, BF16 Gaussian product, second Cholesky QR
+FLAG_SKETCH_FP32, FLAG_GEMM_BF16, FLAG_REORTH = 1, 2, 4
 
 _lib = None
 
@@ -84,8 +86,8 @@ def _check(status, what):
         raise RcqrError(status, what)
 
 
-def workspace_bytes(m, n, s1, s2):
-    return int(lib().rcqr_workspace_bytes(m, n, s1, s2, 0))
+def workspace_bytes(m, n, s1, s2, flags=0):
+    return int(lib().rcqr_workspace_bytes(m, n, s1, s2, flags))
 
 
 def _stream_ptr(stream):
@@ -102,18 +104,20 @@ def _check_matrix(V, m, n, name):
 
 
 class Plan:
-    """A factorization plan for m x n inputs with CountSketch size s1, Gaussian size s2, seed."""
+    """A factorization plan for m x n inputs with CountSketch size s1, Gaussian size s2, seed
+    (flags: FLAG_* bits, 0 = all FP64)."""
 
-    def __init__(self, m, n, s1, s2, seed, device=None, stream=None):
+    def __init__(self, m, n, s1, s2, seed, device=None, stream=None, flags=0):
         self.m, self.n, self.s1, self.s2, self.seed = int(m), int(n), int(s1), int(s2), int(seed)
+        self.flags = int(flags)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-        nbytes = workspace_bytes(self.m, self.n, self.s1, self.s2)
+        nbytes = workspace_bytes(self.m, self.n, self.s1, self.s2, self.flags)
         if nbytes == 0:
             raise RcqrError(E_UNSUPPORTED if 0 < n and n > MAX_N else E_INVALID, "rcqr_workspace_bytes")
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         handle = ctypes.c_void_p()
-        _check(lib().rcqr_plan(ctypes.byref(handle), self.m, self.n, self.s1, self.s2, self.seed, 0,
+        _check(lib().rcqr_plan(ctypes.byref(handle), self.m, self.n, self.s1, self.s2, self.seed, self.flags,
                                ctypes.c_void_p(self.workspace.data_ptr()), nbytes, _stream_ptr(self.stream)), "rcqr_plan")
         self._h = handle
 
@@ -218,10 +222,10 @@ class Plan:
         return a, b
 
 
-def rand_cholqr(V, s1, s2, seed, check=True):
+def rand_cholqr(V, s1, s2, seed, check=True, flags=0):
     """One-shot Algorithm 3: returns (Q, R) for the CUDA float64 matrix V."""
     m, n = V.shape
-    with Plan(m, n, s1, s2, seed, device=V.device) as p:
+    with Plan(m, n, s1, s2, seed, device=V.device, flags=flags) as p:
         Q, R = p.factor(V, check=check)
         torch.cuda.current_stream(V.device).synchronize()
         return Q, R

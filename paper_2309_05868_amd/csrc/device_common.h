@@ -79,4 +79,13 @@ __device__ __forceinline__ double shfl_xor_d(double v, int mask) { return __shfl
 
 __device__ __forceinline__ double shfl_d(double v, int src) { return __shfl(v, src, kWave); }
 
+// The same for the FP32 sketch kernels (overloads, so templates over the element type use one name).
+__device__ __forceinline__ float shfl_xor_d(float v, int mask) { return __shfl_xor(v, mask, kWave); }
+
+__device__ __forceinline__ float shfl_d(float v, int src) { return __shfl(v, src, kWave); }
+
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 }  // namespace rcqr

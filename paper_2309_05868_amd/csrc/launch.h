@@ -21,20 +21,31 @@ hipError_t launch_hist_colscan(int nchunk, int64_t s1, uint32_t* hist, uint32_t*
 hipError_t launch_bucket_scan(const uint32_t* counts, int64_t s1, uint32_t* offsets, uint32_t* cursor, hipStream_t s);
 hipError_t launch_bucket_scatter(int64_t m, int64_t s1, int nchunk, const uint32_t* codes, const uint32_t* offsets, uint32_t* hist,
                                  uint32_t* entries, hipStream_t s);
-// W1[b, :] = sum over the bucket's rows (ascending row order) of sign * V[row, :].
+// W1[b, :] = sum over the bucket's rows (ascending row order) of sign * V[row, :]; the float
+// overload rounds each entry of V to FP32 and accumulates in FP32 (single-precision sketch).
 hipError_t launch_bucket_gather(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, const uint32_t* offsets,
                                 const uint32_t* entries, double* W1, hipStream_t s);
+hipError_t launch_bucket_gather(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, const uint32_t* offsets,
+                                const uint32_t* entries, float* W1, hipStream_t s);
 // Small-s1 CountSketch: per-wave LDS copies of W1; writes one partial W1 per workgroup.
 int countsketch_lds_parts(int64_t m);
 bool countsketch_lds_fits(int64_t s1, int n);
 hipError_t launch_countsketch_lds(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, uint64_t seed,
                                   double* parts, int nparts, hipStream_t s);
+hipError_t launch_countsketch_lds(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, uint64_t seed,
+                                  float* parts, int nparts, hipStream_t s);
 // Wpart[kc] = S2[:, kc-th chunk of KC columns] * W1[chunk, :], S2 generated on the fly.
 hipError_t launch_gauss_gemm(const double* W1, int n, int64_t s1, int64_t s2, uint64_t seed, double scale, int64_t kc_len,
                              int64_t nkc, double* wpart, hipStream_t s);
-// out[i] = sum_{p = 0..nparts-1} parts[p * stride + i] in increasing p.
+// The same product in FP32 on the matrix cores (kc_len a multiple of 32): FP32 operands, or
+// operands rounded to BF16 (bf16 = true); FP32 accumulation.
+hipError_t launch_gauss_mfma(const float* W1, int n, int64_t s1, int64_t s2, uint64_t seed, double scale, int64_t kc_len,
+                             int64_t nkc, bool bf16, float* wpart, hipStream_t s);
+// out[i] = sum_{p = 0..nparts-1} parts[p * stride + i] in increasing p (compensated).
 hipError_t launch_reduce_parts(const double* parts, int64_t nparts, int64_t stride, int64_t len, double* out,
                                hipStream_t s);
+hipError_t launch_reduce_parts(const float* parts, int64_t nparts, int64_t stride, int64_t len, float* out, hipStream_t s);
+hipError_t launch_widen(const float* in, int64_t count, double* out, hipStream_t s);
 hipError_t launch_hash_debug(int64_t row0, int64_t count, int64_t s1, uint64_t seed, int32_t* bucket, int8_t* sign,
                              hipStream_t s);
 hipError_t launch_gaussian_block(int64_t j0, int64_t nj, int64_t k0, int64_t nk, uint64_t seed, double scale,
@@ -46,9 +57,13 @@ hipError_t launch_gaussian_block(int64_t j0, int64_t nj, int64_t k0, int64_t nk,
 // block b reads rows [b*rows_per_block, ...) and writes out + b*n*n.
 hipError_t launch_qr_blocks(const double* in, int64_t ldin, int64_t p_total, int64_t rows_per_block, int n, double* out,
                             int nblocks, hipStream_t s);
+hipError_t launch_qr_blocks(const float* in, int64_t ldin, int64_t p_total, int64_t rows_per_block, int n, float* out,
+                            int nblocks, hipStream_t s);
 // Sign-normalise the Householder R (rows scaled so the diagonal is positive), check its
 // diagonal (status RANK on zero / non-finite), write R0 (n x n) and its packed padded form.
+// The float overload promotes an FP32 Householder R to FP64 first.
 hipError_t launch_finalize_r0(const double* rin, int n, int np, int32_t* info, double* r0, double* r0pk, hipStream_t s);
+hipError_t launch_finalize_r0(const float* rin, int n, int np, int32_t* info, double* r0, double* r0pk, hipStream_t s);
 // Cholesky of the Gram matrix held as compact upper 16x16 blocks; writes G (n x n, upper,
 // lower zero), R1 and its packed padded form, and R = R1 * Rprev into the caller's R
 // (ld ldr).  A non-positive pivot sets status CHOL.

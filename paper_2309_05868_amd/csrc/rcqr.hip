@@ -17,7 +17,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kQrRows = 256;     // rows one Householder workgroup factors
-constexpr int kPhases = 6;
+constexpr int kPhases = 7;
 constexpr int64_t kMaxRows = (int64_t)1 << 31;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -64,10 +64,10 @@ Shape make_shape(int64_t m, int64_t n, int64_t s1, int64_t s2) {
   const int64_t cap = (int64_t)(16u << 20) / (s2 * n * 8);
   if (nkc > cap) nkc = cap;
   if (nkc < 1) nkc = 1;
-  const int64_t maxk = (s1 + 15) / 16;
+  const int64_t maxk = (s1 + 31) / 32;
   if (nkc > maxk) nkc = maxk;
   int64_t kc = (s1 + nkc - 1) / nkc;
-  kc = (kc + 15) / 16 * 16;
+  kc = (kc + 31) / 32 * 32;  // whole k steps of both GEMM kernels
   sh.kc_len = kc;
   sh.nkc = (s1 + kc - 1) / kc;
   sh.qr_blocks0 = (s2 + kQrRows - 1) / kQrRows;
@@ -120,7 +120,14 @@ rcqr_status_t check_shape(int64_t m, int64_t n, int64_t s1, int64_t s2) {
   return RCQR_OK;
 }
 
-const char* const kPhaseNames[kPhases] = {"countsketch", "gaussian", "householder", "trsm_gram", "cholesky", "final"};
+bool flags_valid(uint32_t flags) {
+  const uint32_t known = RCQR_FLAG_SKETCH_FP32 | RCQR_FLAG_GEMM_BF16 | RCQR_FLAG_REORTH;
+  if (flags & ~known) return false;
+  if ((flags & RCQR_FLAG_GEMM_BF16) && !(flags & RCQR_FLAG_SKETCH_FP32)) return false;
+  return true;
+}
+
+const char* const kPhaseNames[kPhases] = {"countsketch", "gaussian", "householder", "trsm_gram", "cholesky", "reorth", "final"};
 
 }  // namespace
 
@@ -167,13 +174,16 @@ static void free_events(rcqr_plan_t p) {
 }
 
 // R0 = Householder R of W (s2 x n): TSQR over 256-row blocks, then sign normalisation.
+// R0 of W (element type T: FP64, or FP32 for the single-precision sketch, promoted to FP64 by
+// the finalize step).
+template <class T>
 static rcqr_status_t run_householder(rcqr_plan_t p) {
   const Shape& sh = p->sh;
   const int n = (int)sh.n;
   hipStream_t s = p->stream;
-  const double* in = p->at<double>(p->L.w);
+  const T* in = p->at<T>(p->L.w);
   int64_t rows = sh.s2, rpb = kQrRows;
-  double* bufs[2] = {p->at<double>(p->L.qra), p->at<double>(p->L.qrb)};
+  T* bufs[2] = {p->at<T>(p->L.qra), p->at<T>(p->L.qrb)};
   int which = 0;
   for (;;) {
     const int64_t nblocks = (rows + rpb - 1) / rpb;
@@ -185,6 +195,43 @@ static rcqr_status_t run_householder(rcqr_plan_t p) {
     rpb = (kQrRows / n) * n;
   }
   RCQR_TRY(launch_finalize_r0(in, n, sh.np, p->at<int32_t>(p->L.info), p->at<double>(p->L.r0), p->at<double>(p->L.r0pk), s));
+  return RCQR_OK;
+}
+
+// Algorithm 1, step 1: W1 = S1 V, then W = S2 W1, in FP64 or (single-precision sketch) FP32.
+template <class T>
+static rcqr_status_t run_sketch(rcqr_plan_t p, const double* V, int64_t ldv) {
+  const Shape& sh = p->sh;
+  const Layout& L = p->L;
+  const int n = (int)sh.n;
+  hipStream_t s = p->stream;
+  T* W1 = p->at<T>(L.w1);
+  if (sh.lds_cs) {
+    T* parts = p->at<T>(L.csparts);
+    RCQR_TRY(launch_countsketch_lds(V, ldv, sh.m, n, sh.s1, p->seed, parts, sh.cs_parts, s));
+    RCQR_TRY(launch_reduce_parts(parts, sh.cs_parts, sh.s1 * sh.n, sh.s1 * sh.n, W1, s));
+  } else {
+    uint32_t* counts = p->at<uint32_t>(L.counts);
+    uint32_t* offsets = p->at<uint32_t>(L.offsets);
+    uint32_t* hist = p->at<uint32_t>(L.hist);
+    uint32_t* codes = p->at<uint32_t>(L.codes);
+    uint32_t* entries = p->at<uint32_t>(L.entries);
+    RCQR_TRY(launch_hash_hist(sh.m, sh.s1, p->seed, sh.nchunk, codes, hist, s));
+    RCQR_TRY(launch_hist_colscan(sh.nchunk, sh.s1, hist, counts, s));
+    RCQR_TRY(launch_bucket_scan(counts, sh.s1, offsets, nullptr, s));
+    RCQR_TRY(launch_bucket_scatter(sh.m, sh.s1, sh.nchunk, codes, offsets, hist, entries, s));
+    RCQR_TRY(launch_bucket_gather(V, ldv, sh.m, n, sh.s1, offsets, entries, W1, s));
+  }
+  if (mark(p, 1) != RCQR_OK) return RCQR_E_HIP;
+  const double scale = 1.0 / std::sqrt((double)sh.s2);
+  T* wpart = p->at<T>(L.wpart);
+  if constexpr (sizeof(T) == 8) {
+    RCQR_TRY(launch_gauss_gemm(W1, n, sh.s1, sh.s2, p->seed, scale, sh.kc_len, sh.nkc, wpart, s));
+  } else {
+    const bool bf16 = (p->flags & RCQR_FLAG_GEMM_BF16) != 0;
+    RCQR_TRY(launch_gauss_mfma(W1, n, sh.s1, sh.s2, p->seed, scale, sh.kc_len, sh.nkc, bf16, wpart, s));
+  }
+  RCQR_TRY(launch_reduce_parts(wpart, sh.nkc, sh.s2 * sh.n, sh.s2 * sh.n, p->at<T>(L.w), s));
   return RCQR_OK;
 }
 
@@ -232,8 +279,7 @@ static rcqr_status_t run_solve(rcqr_plan_t p, const double* X, int64_t ldx, cons
 extern "C" {
 
 size_t rcqr_workspace_bytes(int64_t m, int64_t n, int64_t s1, int64_t s2, uint32_t flags) {
-  (void)flags;
-  if (check_shape(m, n, s1, s2) != RCQR_OK) return 0;
+  if (check_shape(m, n, s1, s2) != RCQR_OK || !flags_valid(flags)) return 0;
   return make_layout(make_shape(m, n, s1, s2)).total;
 }
 
@@ -243,7 +289,7 @@ rcqr_status_t rcqr_plan(rcqr_plan_t* plan, int64_t m, int64_t n, int64_t s1, int
   *plan = nullptr;
   const rcqr_status_t st = check_shape(m, n, s1, s2);
   if (st != RCQR_OK) return st;
-  if (flags != 0) return RCQR_E_INVALID;
+  if (!flags_valid(flags)) return RCQR_E_INVALID;
   const Shape sh = make_shape(m, n, s1, s2);
   const Layout L = make_layout(sh);
   if (d_workspace == nullptr || workspace_bytes < L.total || (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) != 0)
@@ -341,45 +387,36 @@ rcqr_status_t rcqr_factor(rcqr_plan_t p, const double* V, int64_t ldv, double* Q
 
   RCQR_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(info), 16, 0u, s));
   if (mark(p, 0) != RCQR_OK) return RCQR_E_HIP;
-  // Algorithm 1, step 1: W1 = S1 V
-  if (sh.lds_cs) {
-    double* parts = p->at<double>(L.csparts);
-    RCQR_TRY(launch_countsketch_lds(V, ldv, sh.m, n, sh.s1, p->seed, parts, sh.cs_parts, s));
-    RCQR_TRY(launch_reduce_parts(parts, sh.cs_parts, sh.s1 * sh.n, sh.s1 * sh.n, W1, s));
-  } else {
-    uint32_t* counts = p->at<uint32_t>(L.counts);
-    uint32_t* offsets = p->at<uint32_t>(L.offsets);
-    uint32_t* hist = p->at<uint32_t>(L.hist);
-    uint32_t* codes = p->at<uint32_t>(L.codes);
-    uint32_t* entries = p->at<uint32_t>(L.entries);
-    RCQR_TRY(launch_hash_hist(sh.m, sh.s1, p->seed, sh.nchunk, codes, hist, s));
-    RCQR_TRY(launch_hist_colscan(sh.nchunk, sh.s1, hist, counts, s));
-    RCQR_TRY(launch_bucket_scan(counts, sh.s1, offsets, nullptr, s));
-    RCQR_TRY(launch_bucket_scatter(sh.m, sh.s1, sh.nchunk, codes, offsets, hist, entries, s));
-    RCQR_TRY(launch_bucket_gather(V, ldv, sh.m, n, sh.s1, offsets, entries, W1, s));
-  }
-  if (mark(p, 1) != RCQR_OK) return RCQR_E_HIP;
-  // Algorithm 1, step 1: W = S2 W1
-  {
-    const double scale = 1.0 / std::sqrt((double)sh.s2);
-    double* wpart = p->at<double>(L.wpart);
-    RCQR_TRY(launch_gauss_gemm(W1, n, sh.s1, sh.s2, p->seed, scale, sh.kc_len, sh.nkc, wpart, s));
-    RCQR_TRY(launch_reduce_parts(wpart, sh.nkc, sh.s2 * sh.n, sh.s2 * sh.n, p->at<double>(L.w), s));
-  }
+  const bool fp32 = (p->flags & RCQR_FLAG_SKETCH_FP32) != 0;
+  const bool reorth = (p->flags & RCQR_FLAG_REORTH) != 0;
+  // Algorithm 1, step 1: W1 = S1 V, W = S2 W1
+  if ((fp32 ? run_sketch<float>(p, V, ldv) : run_sketch<double>(p, V, ldv)) != RCQR_OK) return RCQR_E_HIP;
   if (mark(p, 2) != RCQR_OK) return RCQR_E_HIP;
   // Algorithm 1, step 2: R0 = hhqr(W)
-  if (run_householder(p) != RCQR_OK) return RCQR_E_HIP;
+  if ((fp32 ? run_householder<float>(p) : run_householder<double>(p)) != RCQR_OK) return RCQR_E_HIP;
   if (mark(p, 3) != RCQR_OK) return RCQR_E_HIP;
   // Algorithm 1, step 3 + Algorithm 2, step 1: Q0 = V R0^{-1}, G = Q0^T Q0
   if (run_gram(p, V, ldv, p->at<double>(L.r0pk), Q, ldq) != RCQR_OK) return RCQR_E_HIP;
   if (mark(p, 4) != RCQR_OK) return RCQR_E_HIP;
   // Algorithm 2, step 2 and Algorithm 3, step 3: R1 = chol(G), R = R1 R0
+  double* r_first = reorth ? p->at<double>(L.rtmp) : R;
+  const int64_t ld_first = reorth ? n : ldr;
   RCQR_TRY(launch_cholesky(p->at<double>(L.gc), n, sh.np, p->at<double>(L.r0), 0.0, info, p->at<double>(L.g),
-                           p->at<double>(L.r1), p->at<double>(L.r1pk), R, ldr, s));
+                           p->at<double>(L.r1), p->at<double>(L.r1pk), r_first, ld_first, s));
   if (mark(p, 5) != RCQR_OK) return RCQR_E_HIP;
-  // Algorithm 2, step 3 on Q0: Q = Q0 R1^{-1}
-  if (run_final(p, V, ldv, p->at<double>(L.r0pk), p->at<double>(L.r1pk), Q, ldq) != RCQR_OK) return RCQR_E_HIP;
+  const double* first_pk = p->at<double>(L.r0pk);
+  if (reorth) {
+    // one more Cholesky QR: Q1 = V Rc^{-1} with Rc = R1 R0, R2 = chol(Q1^T Q1), R = R2 Rc
+    RCQR_TRY(launch_finalize_r0(p->at<double>(L.rtmp), n, sh.np, info, p->at<double>(L.ra), p->at<double>(L.rapk), s));
+    if (run_gram(p, V, ldv, p->at<double>(L.rapk), Q, ldq) != RCQR_OK) return RCQR_E_HIP;
+    RCQR_TRY(launch_cholesky(p->at<double>(L.gc), n, sh.np, p->at<double>(L.ra), 0.0, info, p->at<double>(L.g),
+                             p->at<double>(L.r1), p->at<double>(L.r1pk), R, ldr, s));
+    first_pk = p->at<double>(L.rapk);
+  }
   if (mark(p, 6) != RCQR_OK) return RCQR_E_HIP;
+  // Algorithm 2, step 3 on Q0 (or Q1): Q = Q0 R1^{-1}
+  if (run_final(p, V, ldv, first_pk, p->at<double>(L.r1pk), Q, ldq) != RCQR_OK) return RCQR_E_HIP;
+  if (mark(p, 7) != RCQR_OK) return RCQR_E_HIP;
   if (p->cap > 0) ++p->recorded;
   return RCQR_OK;
 }
@@ -472,8 +509,15 @@ rcqr_status_t rcqr_intermediates(rcqr_plan_t p, double* d_W1, double* d_W, doubl
             {d_R0, p->L.r0, nn},
             {d_G, p->L.g, nn},
             {d_R1, p->L.r1, nn}};
-  for (auto& e : c)
-    if (e.dst) RCQR_TRY(hipMemcpyAsync(e.dst, p->ws + e.off, e.bytes, hipMemcpyDeviceToDevice, p->stream));
+  const bool fp32 = (p->flags & RCQR_FLAG_SKETCH_FP32) != 0;
+  for (int i = 0; i < 5; ++i) {
+    auto& e = c[i];
+    if (!e.dst) continue;
+    if (fp32 && i < 2)  // W1 and W of the single-precision sketch are FP32 in the workspace
+      RCQR_TRY(launch_widen(reinterpret_cast<const float*>(p->ws + e.off), (int64_t)(e.bytes / 8), e.dst, p->stream));
+    else
+      RCQR_TRY(hipMemcpyAsync(e.dst, p->ws + e.off, e.bytes, hipMemcpyDeviceToDevice, p->stream));
+  }
   return RCQR_OK;
 }
 

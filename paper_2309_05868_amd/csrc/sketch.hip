@@ -226,10 +226,12 @@ __device__ void wave_bitonic_sort(uint32_t* keys, int N, int lane) {
   }
 }
 
-// Accumulate sorted entries keys[0..cnt) into acc: lane group g takes entries g, g+G, ...
-template <int NPL>
+// Accumulate sorted entries keys[0..cnt) into acc (element type T: FP64, or FP32 for the
+// single-precision sketch, where each V entry is rounded to FP32 before it is added): lane
+// group g takes entries g, g+G, ...
+template <int NPL, class T>
 __device__ __forceinline__ void gather_rows(const uint32_t* keys, int cnt, const double* __restrict__ V, int64_t ldv, int n,
-                                            int lane, double (&acc)[NPL > 64 ? 2 : 1]) {
+                                            int lane, T (&acc)[NPL > 64 ? 2 : 1]) {
   constexpr int G = NPL >= 64 ? 1 : 64 / NPL;
   const int g = NPL >= 64 ? 0 : lane / NPL;
   const int c = NPL >= 64 ? lane : lane % NPL;
@@ -251,34 +253,38 @@ __device__ __forceinline__ void gather_rows(const uint32_t* keys, int cnt, const
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const bool neg = kk[u] & 1u;
-        acc[0] += neg ? -v[u][0] : v[u][0];
-        acc[1] += neg ? -v[u][1] : v[u][1];
+        const T x0 = (T)v[u][0], x1 = (T)v[u][1];
+        acc[0] += neg ? -x0 : x0;
+        acc[1] += neg ? -x1 : x1;
       }
     } else {
       double v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) v[u] = c < n ? V[(int64_t)(kk[u] >> 1) * ldv + c] : 0.0;
 #pragma unroll
-      for (int u = 0; u < U; ++u) acc[0] += (kk[u] & 1u) ? -v[u] : v[u];
+      for (int u = 0; u < U; ++u) {
+        const T x = (T)v[u];
+        acc[0] += (kk[u] & 1u) ? -x : x;
+      }
     }
   }
   for (; e < cnt; e += G) {
     const uint32_t k = keys[e];
     const double* row = V + (int64_t)(k >> 1) * ldv;
     const bool neg = k & 1u;
-    const double v0 = c < n ? row[c] : 0.0;
+    const T v0 = (T)(c < n ? row[c] : 0.0);
     acc[0] += neg ? -v0 : v0;
     if constexpr (NPL > 64) {
-      const double v1 = c + 64 < n ? row[c + 64] : 0.0;
+      const T v1 = (T)(c + 64 < n ? row[c + 64] : 0.0);
       acc[1] += neg ? -v1 : v1;
     }
   }
 }
 
-template <int NPL>
+template <int NPL, class T>
 __global__ __launch_bounds__(256) void bucket_gather_kernel(const double* __restrict__ V, int64_t ldv, int64_t m, int n, int64_t s1,
                                                             const uint32_t* __restrict__ offsets,
-                                                            const uint32_t* __restrict__ entries, double* __restrict__ W1) {
+                                                            const uint32_t* __restrict__ entries, T* __restrict__ W1) {
   __shared__ uint32_t keys_all[kGatherWaves][kSortCap];
   const int wave = threadIdx.x / kWave;
   const int lane = lane_id();
@@ -287,9 +293,9 @@ __global__ __launch_bounds__(256) void bucket_gather_kernel(const double* __rest
   uint32_t* keys = keys_all[wave];
   const uint32_t beg = offsets[b];
   const int64_t L = (int64_t)offsets[b + 1] - beg;
-  double acc[NPL > 64 ? 2 : 1];
-  acc[0] = 0.0;
-  if constexpr (NPL > 64) acc[1] = 0.0;
+  T acc[NPL > 64 ? 2 : 1];
+  acc[0] = T(0);
+  if constexpr (NPL > 64) acc[1] = T(0);
 
   if (L <= kSortCap) {
     int N = 1;
@@ -297,7 +303,7 @@ __global__ __launch_bounds__(256) void bucket_gather_kernel(const double* __rest
     for (int i = lane; i < N; i += kWave) keys[i] = i < L ? entries[beg + i] : 0xFFFFFFFFu;
     wave_lds_sync();
     wave_bitonic_sort(keys, N, lane);
-    gather_rows<NPL>(keys, (int)L, V, ldv, n, lane, acc);
+    gather_rows<NPL, T>(keys, (int)L, V, ldv, n, lane, acc);
   } else {
     // Windows of rows [lo, hi) small enough to sort; together they visit the bucket's
     // entries in ascending row order.
@@ -337,7 +343,7 @@ __global__ __launch_bounds__(256) void bucket_gather_kernel(const double* __rest
       for (int i = (int)cnt + lane; i < N; i += kWave) keys[i] = 0xFFFFFFFFu;
       wave_lds_sync();
       wave_bitonic_sort(keys, N, lane);
-      gather_rows<NPL>(keys, (int)cnt, V, ldv, n, lane, acc);
+      gather_rows<NPL, T>(keys, (int)cnt, V, ldv, n, lane, acc);
       wave_lds_sync();
       remaining -= cnt;
       lo = hi;
@@ -354,20 +360,31 @@ __global__ __launch_bounds__(256) void bucket_gather_kernel(const double* __rest
   }
 }
 
-hipError_t launch_bucket_gather(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, const uint32_t* offsets,
-                                const uint32_t* entries, double* W1, hipStream_t s) {
+template <class T>
+static hipError_t bucket_gather_any(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, const uint32_t* offsets,
+                                    const uint32_t* entries, T* W1, hipStream_t s) {
   const dim3 grid((unsigned)((s1 + kGatherWaves - 1) / kGatherWaves)), block(256);
   if (n <= 8)
-    hipLaunchKernelGGL(bucket_gather_kernel<8>, grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, W1);
+    hipLaunchKernelGGL((bucket_gather_kernel<8, T>), grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, W1);
   else if (n <= 16)
-    hipLaunchKernelGGL(bucket_gather_kernel<16>, grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, W1);
+    hipLaunchKernelGGL((bucket_gather_kernel<16, T>), grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, W1);
   else if (n <= 32)
-    hipLaunchKernelGGL(bucket_gather_kernel<32>, grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, W1);
+    hipLaunchKernelGGL((bucket_gather_kernel<32, T>), grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, W1);
   else if (n <= 64)
-    hipLaunchKernelGGL(bucket_gather_kernel<64>, grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, W1);
+    hipLaunchKernelGGL((bucket_gather_kernel<64, T>), grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, W1);
   else
-    hipLaunchKernelGGL(bucket_gather_kernel<128>, grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, W1);
+    hipLaunchKernelGGL((bucket_gather_kernel<128, T>), grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, W1);
   return hipGetLastError();
+}
+
+hipError_t launch_bucket_gather(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, const uint32_t* offsets,
+                                const uint32_t* entries, double* W1, hipStream_t s) {
+  return bucket_gather_any(V, ldv, m, n, s1, offsets, entries, W1, s);
+}
+
+hipError_t launch_bucket_gather(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, const uint32_t* offsets,
+                                const uint32_t* entries, float* W1, hipStream_t s) {
+  return bucket_gather_any(V, ldv, m, n, s1, offsets, entries, W1, s);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -391,16 +408,16 @@ static int npl_of(int n) {
 
 bool countsketch_lds_fits(int64_t s1, int n) { return n <= 64 && s1 * npl_of(n) <= kCsLdsDoubles; }
 
-template <int NPL>
+template <int NPL, class T>
 __global__ __launch_bounds__(256) void countsketch_lds_kernel(const double* __restrict__ V, int64_t ldv, int64_t m, int n, int64_t s1,
-                                                              uint64_t seed, double* __restrict__ parts) {
-  __shared__ double w1[4][kCsLdsDoubles];
+                                                              uint64_t seed, T* __restrict__ parts) {
+  __shared__ T w1[4][kCsLdsDoubles];
   __shared__ uint32_t codes[4][kCsChunk];
   constexpr int RB = kWave / NPL;  // rows per batch
   const int wave = threadIdx.x / kWave, lane = lane_id();
   const int q = lane / NPL, c = lane % NPL;
-  double* mine = w1[wave];
-  for (int i = lane; i < s1 * NPL; i += kWave) mine[i] = 0.0;
+  T* mine = w1[wave];
+  for (int i = lane; i < s1 * NPL; i += kWave) mine[i] = T(0);
   // rows of this workgroup
   const int64_t per = ((m + gridDim.x - 1) / gridDim.x + kCsChunk - 1) / kCsChunk * kCsChunk;
   const int64_t r_beg = (int64_t)blockIdx.x * per;
@@ -420,17 +437,17 @@ __global__ __launch_bounds__(256) void countsketch_lds_kernel(const double* __re
     for (int b0 = 0; b0 < rows; b0 += RB) {
       const int rq = b0 + q;
       const bool valid = rq < rows && c < n;
-      double v = valid ? V[(base + rq) * ldv + c] : 0.0;
+      T v = (T)(valid ? V[(base + rq) * ldv + c] : 0.0);
       const uint32_t code = rq < rows ? codes[wave][rq] : 0u;
       if (code & 1u) v = -v;
       const uint32_t bkt = code >> 1;
       if constexpr (RB > 1) {
         // combine rows of this batch with the same bucket into the lowest such row, in row order
         bool leader = rq < rows;
-        double tot = v;
+        T tot = v;
 #pragma unroll
         for (int q2 = 0; q2 < RB; ++q2) {
-          const double v2 = shfl_d(v, q2 * NPL + c);
+          const T v2 = shfl_d(v, q2 * NPL + c);
           const int rq2 = b0 + q2;
           const bool same = rq2 < rows && (codes[wave][rq2 < rows ? rq2 : 0] >> 1) == bkt;
           if (same && q2 < q) leader = false;
@@ -445,7 +462,7 @@ __global__ __launch_bounds__(256) void countsketch_lds_kernel(const double* __re
   }
   __syncthreads();
   // fixed-order sum of the four wave copies -> this workgroup's partial
-  double* out = parts + (int64_t)blockIdx.x * s1 * n;
+  T* out = parts + (int64_t)blockIdx.x * s1 * n;
   for (int64_t i = threadIdx.x; i < s1 * n; i += blockDim.x) {
     const int64_t b = i / n, cc = i % n;
     const int64_t o = b * NPL + cc;
@@ -453,17 +470,28 @@ __global__ __launch_bounds__(256) void countsketch_lds_kernel(const double* __re
   }
 }
 
-hipError_t launch_countsketch_lds(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, uint64_t seed, double* parts,
-                                  int nparts, hipStream_t s) {
+template <class T>
+static hipError_t countsketch_lds_any(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, uint64_t seed, T* parts,
+                                      int nparts, hipStream_t s) {
   const dim3 grid((unsigned)nparts), block(256);
   switch (npl_of(n)) {
-    case 8: hipLaunchKernelGGL(countsketch_lds_kernel<8>, grid, block, 0, s, V, ldv, m, n, s1, seed, parts); break;
-    case 16: hipLaunchKernelGGL(countsketch_lds_kernel<16>, grid, block, 0, s, V, ldv, m, n, s1, seed, parts); break;
-    case 32: hipLaunchKernelGGL(countsketch_lds_kernel<32>, grid, block, 0, s, V, ldv, m, n, s1, seed, parts); break;
-    case 64: hipLaunchKernelGGL(countsketch_lds_kernel<64>, grid, block, 0, s, V, ldv, m, n, s1, seed, parts); break;
+    case 8: hipLaunchKernelGGL((countsketch_lds_kernel<8, T>), grid, block, 0, s, V, ldv, m, n, s1, seed, parts); break;
+    case 16: hipLaunchKernelGGL((countsketch_lds_kernel<16, T>), grid, block, 0, s, V, ldv, m, n, s1, seed, parts); break;
+    case 32: hipLaunchKernelGGL((countsketch_lds_kernel<32, T>), grid, block, 0, s, V, ldv, m, n, s1, seed, parts); break;
+    case 64: hipLaunchKernelGGL((countsketch_lds_kernel<64, T>), grid, block, 0, s, V, ldv, m, n, s1, seed, parts); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_countsketch_lds(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, uint64_t seed, double* parts,
+                                  int nparts, hipStream_t s) {
+  return countsketch_lds_any(V, ldv, m, n, s1, seed, parts, nparts, s);
+}
+
+hipError_t launch_countsketch_lds(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, uint64_t seed, float* parts,
+                                  int nparts, hipStream_t s) {
+  return countsketch_lds_any(V, ldv, m, n, s1, seed, parts, nparts, s);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -541,6 +569,126 @@ hipError_t launch_gauss_gemm(const double* W1, int n, int64_t s1, int64_t s2, ui
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------------------------------
+// Gaussian sketch GEMM of the single-precision sketch on the matrix cores, split over s1 like
+// the FP64 kernel: Wpart[kc] = S2[:, chunk] W1[chunk, :] with FP32 accumulation.  S2 entries are
+// the FP64 contract values rounded to FP32 (and, for the BF16 variant, both operands rounded
+// on to BF16).  Wave w owns S2 rows 16w..16w+15 of the workgroup's 64-row block and every
+// 16-column block of W: v_mfma_f32_16x16x4f32 (8 per 32-wide k step) or
+// v_mfma_f32_16x16x32_bf16 (one per step).  Operand lanes: row/column = lane % 16, k group =
+// lane / 16 (the same k order on both operands, so any k permutation of the instruction cancels).
+// Result lane l, element e: row 4 (l / 16) + e, column l % 16.
+// ------------------------------------------------------------------------------------------
+constexpr int kMmK = 32;  // k step of the matrix-core kernel
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <int NP, bool BF16>
+__global__ __launch_bounds__(256) void gauss_mfma_kernel(const float* __restrict__ W1, int n, int64_t s1, int64_t s2, uint64_t seed,
+                                                         double scale, int64_t kc_len, float* __restrict__ wpart) {
+  __shared__ float st[kGemmRows][kMmK + 1];  // S2 tile, [row j][k]
+  __shared__ float wt[NP][kMmK + 1];         // W1 tile transposed, [column c][k]
+  constexpr int NCB = NP / 16;
+  const int t = threadIdx.x, wave = t / kWave, lane = lane_id();
+  const int li = lane % 16, lq = lane / 16;
+  const int64_t kc = blockIdx.x, rb = blockIdx.y;
+  const int64_t k_beg = kc * kc_len;
+  const int64_t k_end = k_beg + kc_len < s1 ? k_beg + kc_len : s1;
+  f32x4 acc[NCB];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t k0 = k_beg; k0 < k_end; k0 += kMmK) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {  // 512 Philox blocks: (k, block of 4 rows)
+      const int idx = t + 256 * h;
+      const int kk = idx % kMmK, jb = idx / kMmK;  // jb in 0..15
+      const int64_t k = k0 + kk;
+      const int64_t jblk = rb * (kGemmRows / 4) + jb;
+      double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
+      if (k < k_end) {
+        const Block4 y = philox4x64_10((uint64_t)k, (uint64_t)jblk, 0, kTagGaussian, seed, 0);
+        box_muller(y.y0, y.y1, z0, z1);
+        box_muller(y.y2, y.y3, z2, z3);
+      }
+      const int64_t j = 4 * jblk;
+      const bool kin = k < k_end;
+      st[4 * jb + 0][kk] = (kin && j + 0 < s2) ? (float)(z0 * scale) : 0.f;
+      st[4 * jb + 1][kk] = (kin && j + 1 < s2) ? (float)(z1 * scale) : 0.f;
+      st[4 * jb + 2][kk] = (kin && j + 2 < s2) ? (float)(z2 * scale) : 0.f;
+      st[4 * jb + 3][kk] = (kin && j + 3 < s2) ? (float)(z3 * scale) : 0.f;
+    }
+    for (int i = t; i < kMmK * NP; i += 256) {
+      const int kk = i / NP, c = i % NP;
+      const int64_t k = k0 + kk;
+      wt[c][kk] = (k < k_end && c < n) ? W1[k * n + c] : 0.f;
+    }
+    __syncthreads();
+    const float* arow = st[16 * wave + li];
+    if constexpr (BF16) {
+      bf16x8 a;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[q] = (__bf16)arow[8 * lq + q];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const float* brow = wt[16 * cb + li];
+        bf16x8 b;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) b[q] = (__bf16)brow[8 * lq + q];
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[cb], 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < kMmK / 4; ++ks) {
+        const float a = arow[4 * ks + lq];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, wt[16 * cb + li][4 * ks + lq], acc[cb], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) {
+    const int c = 16 * cb + li;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t j = rb * kGemmRows + 16 * wave + 4 * lq + e;
+      if (j < s2 && c < n) wpart[(kc * s2 + j) * n + c] = acc[cb][e];
+    }
+  }
+}
+
+hipError_t launch_gauss_mfma(const float* W1, int n, int64_t s1, int64_t s2, uint64_t seed, double scale, int64_t kc_len,
+                             int64_t nkc, bool bf16, float* wpart, hipStream_t s) {
+  if (kc_len % kMmK != 0) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)nkc, (unsigned)((s2 + kGemmRows - 1) / kGemmRows)), block(256);
+  const int np = n <= 16 ? 16 : n <= 32 ? 32 : n <= 64 ? 64 : 128;
+#define RCQR_GAUSS_MFMA(NP_)                                                                                          \
+  if (np == NP_) {                                                                                                    \
+    if (bf16)                                                                                                         \
+      hipLaunchKernelGGL((gauss_mfma_kernel<NP_, true>), grid, block, 0, s, W1, n, s1, s2, seed, scale, kc_len, wpart); \
+    else                                                                                                              \
+      hipLaunchKernelGGL((gauss_mfma_kernel<NP_, false>), grid, block, 0, s, W1, n, s1, s2, seed, scale, kc_len, wpart); \
+  }
+  RCQR_GAUSS_MFMA(16)
+  RCQR_GAUSS_MFMA(32)
+  RCQR_GAUSS_MFMA(64)
+  RCQR_GAUSS_MFMA(128)
+#undef RCQR_GAUSS_MFMA
+  return hipGetLastError();
+}
+
+// Widen an FP32 array to FP64 (inspection of the single-precision sketch's intermediates).
+__global__ void widen_kernel(const float* __restrict__ in, int64_t count, double* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) out[i] = in[i];
+}
+
+hipError_t launch_widen(const float* in, int64_t count, double* out, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(widen_kernel, dim3(grid_for(count, 256)), dim3(256), 0, s, in, count, out);
+  return hipGetLastError();
+}
+
 // Debug: a block of S2 entries.
 __global__ void gaussian_block_kernel(int64_t j0, int64_t nj, int64_t k0, int64_t nk, uint64_t seed, double scale, double* out) {
   const int64_t total = nj * nk;
@@ -568,25 +716,26 @@ hipError_t launch_gaussian_block(int64_t j0, int64_t nj, int64_t k0, int64_t nk,
 // rounding error of each addition is recovered exactly (TwoSum) and added back at the end, so
 // the result does not degrade with the number of partials.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void reduce_parts_kernel(const double* __restrict__ parts, int64_t nparts, int64_t stride, int64_t len,
-                                                           double* __restrict__ out) {
+template <class T>
+__global__ __launch_bounds__(256) void reduce_parts_kernel(const T* __restrict__ parts, int64_t nparts, int64_t stride, int64_t len,
+                                                           T* __restrict__ out) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x) {
-    double sum = 0.0, comp = 0.0;
+    T sum = T(0), comp = T(0);
     int64_t p = 0;
     for (; p + 8 <= nparts; p += 8) {
-      double v[8];
+      T v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) v[u] = parts[(p + u) * stride + i];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const double t = sum + v[u];
+        const T t = sum + v[u];
         comp += (fabs(sum) >= fabs(v[u])) ? ((sum - t) + v[u]) : ((v[u] - t) + sum);
         sum = t;
       }
     }
     for (; p < nparts; ++p) {
-      const double x = parts[p * stride + i];
-      const double t = sum + x;
+      const T x = parts[p * stride + i];
+      const T t = sum + x;
       comp += (fabs(sum) >= fabs(x)) ? ((sum - t) + x) : ((x - t) + sum);
       sum = t;
     }
@@ -596,7 +745,13 @@ __global__ __launch_bounds__(256) void reduce_parts_kernel(const double* __restr
 
 hipError_t launch_reduce_parts(const double* parts, int64_t nparts, int64_t stride, int64_t len, double* out, hipStream_t s) {
   if (len <= 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_parts_kernel, dim3(grid_for(len, 256, 2048)), dim3(256), 0, s, parts, nparts, stride, len, out);
+  hipLaunchKernelGGL(reduce_parts_kernel<double>, dim3(grid_for(len, 256, 2048)), dim3(256), 0, s, parts, nparts, stride, len, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_parts(const float* parts, int64_t nparts, int64_t stride, int64_t len, float* out, hipStream_t s) {
+  if (len <= 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_parts_kernel<float>, dim3(grid_for(len, 256, 2048)), dim3(256), 0, s, parts, nparts, stride, len, out);
   return hipGetLastError();
 }
 

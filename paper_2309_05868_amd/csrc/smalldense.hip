@@ -29,49 +29,49 @@ namespace rcqr {
 // ------------------------------------------------------------------------------------------
 constexpr int kQrMaxRows = 256;
 
-template <int TPC>
-__device__ __forceinline__ double group_sum(double v) {
+template <int TPC, class T>
+__device__ __forceinline__ T group_sum(T v) {
 #pragma unroll
   for (int off = TPC / 2; off > 0; off >>= 1) v += shfl_xor_d(v, off);
   return v;
 }
 
-template <int NPAD, int TPC>
-__global__ __launch_bounds__(NPAD * TPC) void qr_block_kernel(const double* __restrict__ in, int64_t ldin, int64_t p_total,
-                                                             int64_t rows_per_block, int n, double* __restrict__ out) {
+template <int NPAD, int TPC, class T>
+__global__ __launch_bounds__(NPAD * TPC) void qr_block_kernel(const T* __restrict__ in, int64_t ldin, int64_t p_total,
+                                                             int64_t rows_per_block, int n, T* __restrict__ out) {
   static_assert(TPC <= 64 && (64 % TPC) == 0, "a column's threads must sit in one wave");
   constexpr int EPT = kQrMaxRows / TPC;
   constexpr int CPW = 64 / TPC;  // columns per wave = panel width
-  __shared__ double vbuf[2][CPW][kQrMaxRows];
-  __shared__ double taub[2][CPW];
+  __shared__ T vbuf[2][CPW][kQrMaxRows];
+  __shared__ T taub[2][CPW];
   const int t = threadIdx.x;
   const int c = t / TPC, rg = t % TPC;
   const int wave = t / kWave;
   const int64_t r_beg = (int64_t)blockIdx.x * rows_per_block;
   const int64_t p64 = p_total - r_beg < rows_per_block ? p_total - r_beg : rows_per_block;
   const int p = (int)p64;
-  const double* A0 = in + r_beg * ldin;
-  double a[EPT];
+  const T* A0 = in + r_beg * ldin;
+  T a[EPT];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int r = rg + TPC * e;
-    a[e] = (r < p && c < n) ? A0[(int64_t)r * ldin + c] : 0.0;
+    a[e] = (r < p && c < n) ? A0[(int64_t)r * ldin + c] : T(0);
   }
   const int steps = n < p ? n : p;
   // apply reflector (vb, tau) with leading row j to this thread's column
-  auto apply = [&](const double* vb, double tau, int j) {
-    double d = 0.0;
+  auto apply = [&](const T* vb, T tau, int j) {
+    T d = T(0);
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       const int r = rg + TPC * e;
-      if (r >= j && r < p) d = __builtin_fma(vb[r], a[e], d);
+      if (r >= j && r < p) d = fma_t(vb[r], a[e], d);
     }
     d = group_sum<TPC>(d);
-    const double tw = tau * d;
+    const T tw = tau * d;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       const int r = rg + TPC * e;
-      if (r >= j && r < p) a[e] = __builtin_fma(-tw, vb[r], a[e]);
+      if (r >= j && r < p) a[e] = fma_t(-tw, vb[r], a[e]);
     }
   };
   for (int q = 0, pi = 0; q < steps; q += CPW, ++pi) {
@@ -81,30 +81,30 @@ __global__ __launch_bounds__(NPAD * TPC) void qr_block_kernel(const double* __re
       for (int j = q; j < qend; ++j) {
         const int jj = j - q;
         if (c == j) {
-          double ss = 0.0, alpha = 0.0;
+          T ss = T(0), alpha = T(0);
 #pragma unroll
           for (int e = 0; e < EPT; ++e) {
             const int r = rg + TPC * e;
-            if (r > j) ss = __builtin_fma(a[e], a[e], ss);
+            if (r > j) ss = fma_t(a[e], a[e], ss);
             if (r == j) alpha = a[e];
           }
           ss = group_sum<TPC>(ss);
           alpha = group_sum<TPC>(alpha);  // only the owner of row j holds a nonzero term
-          double tau = 0.0, beta = alpha, scal = 0.0;
-          if (ss != 0.0) {
-            beta = -copysign(sqrt(__builtin_fma(alpha, alpha, ss)), alpha);
+          T tau = T(0), beta = alpha, scal = T(0);
+          if (ss != T(0)) {
+            beta = -copysign(sqrt(fma_t(alpha, alpha, ss)), alpha);
             tau = (beta - alpha) / beta;
-            scal = 1.0 / (alpha - beta);
+            scal = T(1) / (alpha - beta);
           }
 #pragma unroll
           for (int e = 0; e < EPT; ++e) {
             const int r = rg + TPC * e;
             if (r == j) {
-              vbuf[buf][jj][r] = 1.0;
+              vbuf[buf][jj][r] = T(1);
               a[e] = beta;
             } else if (r > j) {
               vbuf[buf][jj][r] = a[e] * scal;
-              a[e] = 0.0;
+              a[e] = T(0);
             }
           }
           if (rg == 0) taub[buf][jj] = tau;
@@ -118,29 +118,40 @@ __global__ __launch_bounds__(NPAD * TPC) void qr_block_kernel(const double* __re
       for (int j = q; j < qend; ++j) apply(vbuf[buf][j - q], taub[buf][j - q], j);
     }
   }
-  double* R = out + (int64_t)blockIdx.x * n * n;
+  T* R = out + (int64_t)blockIdx.x * n * n;
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int r = rg + TPC * e;
-    if (r < n && c < n) R[r * n + c] = (c >= r) ? a[e] : 0.0;
+    if (r < n && c < n) R[r * n + c] = (c >= r) ? a[e] : T(0);
   }
+}
+
+template <class T>
+static hipError_t qr_blocks_any(const T* in, int64_t ldin, int64_t p_total, int64_t rows_per_block, int n, T* out, int nblocks,
+                                hipStream_t s) {
+  if (rows_per_block > kQrMaxRows || n > RCQR_MAX_N || n < 1) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)nblocks);
+  if (n <= 8)
+    hipLaunchKernelGGL((qr_block_kernel<8, 64, T>), grid, dim3(8 * 64), 0, s, in, ldin, p_total, rows_per_block, n, out);
+  else if (n <= 16)
+    hipLaunchKernelGGL((qr_block_kernel<16, 16, T>), grid, dim3(16 * 16), 0, s, in, ldin, p_total, rows_per_block, n, out);
+  else if (n <= 32)
+    hipLaunchKernelGGL((qr_block_kernel<32, 32, T>), grid, dim3(32 * 32), 0, s, in, ldin, p_total, rows_per_block, n, out);
+  else if (n <= 64)
+    hipLaunchKernelGGL((qr_block_kernel<64, 16, T>), grid, dim3(64 * 16), 0, s, in, ldin, p_total, rows_per_block, n, out);
+  else
+    hipLaunchKernelGGL((qr_block_kernel<128, 8, T>), grid, dim3(128 * 8), 0, s, in, ldin, p_total, rows_per_block, n, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_qr_blocks(const double* in, int64_t ldin, int64_t p_total, int64_t rows_per_block, int n, double* out,
                             int nblocks, hipStream_t s) {
-  if (rows_per_block > kQrMaxRows || n > RCQR_MAX_N || n < 1) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)nblocks);
-  if (n <= 8)
-    hipLaunchKernelGGL((qr_block_kernel<8, 64>), grid, dim3(8 * 64), 0, s, in, ldin, p_total, rows_per_block, n, out);
-  else if (n <= 16)
-    hipLaunchKernelGGL((qr_block_kernel<16, 16>), grid, dim3(16 * 16), 0, s, in, ldin, p_total, rows_per_block, n, out);
-  else if (n <= 32)
-    hipLaunchKernelGGL((qr_block_kernel<32, 32>), grid, dim3(32 * 32), 0, s, in, ldin, p_total, rows_per_block, n, out);
-  else if (n <= 64)
-    hipLaunchKernelGGL((qr_block_kernel<64, 16>), grid, dim3(64 * 16), 0, s, in, ldin, p_total, rows_per_block, n, out);
-  else
-    hipLaunchKernelGGL((qr_block_kernel<128, 8>), grid, dim3(128 * 8), 0, s, in, ldin, p_total, rows_per_block, n, out);
-  return hipGetLastError();
+  return qr_blocks_any(in, ldin, p_total, rows_per_block, n, out, nblocks, s);
+}
+
+hipError_t launch_qr_blocks(const float* in, int64_t ldin, int64_t p_total, int64_t rows_per_block, int n, float* out,
+                            int nblocks, hipStream_t s) {
+  return qr_blocks_any(in, ldin, p_total, rows_per_block, n, out, nblocks, s);
 }
 
 // Offset of row k in the packed np x np upper-triangular format.
@@ -171,13 +182,15 @@ __device__ __forceinline__ void put_packed(double* pk, int np, int n, int r, int
 // ------------------------------------------------------------------------------------------
 // R0: positive diagonal, rank check, packed padded copy.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void finalize_r0_kernel(const double* __restrict__ rin, int n, int np, int32_t* __restrict__ info,
+template <class T>
+__global__ __launch_bounds__(256) void finalize_r0_kernel(const T* __restrict__ rin, int n, int np, int32_t* __restrict__ info,
                                                           double* __restrict__ r0, double* __restrict__ r0pk) {
   __shared__ int bad;  // first failing column (1-based), or a value > n
+  if (info[0] != 0) return;  // an earlier step failed: keep its status
   if (threadIdx.x == 0) bad = n + 1;
   __syncthreads();
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    const double d = rin[j * n + j];
+    const double d = (double)rin[j * n + j];
     if (!(d != 0.0) || !isfinite(d)) atomicMin(&bad, j + 1);
   }
   __syncthreads();
@@ -189,8 +202,9 @@ __global__ __launch_bounds__(256) void finalize_r0_kernel(const double* __restri
     const int r = i / np, c = i % np;
     double v = 0.0;
     if (r < n && c < n) {
-      const double d = rin[r * n + r];
-      v = c >= r ? (d < 0.0 ? -rin[r * n + c] : rin[r * n + c]) : 0.0;
+      const double d = (double)rin[r * n + r];
+      const double x = (double)rin[r * n + c];
+      v = c >= r ? (d < 0.0 ? -x : x) : 0.0;
       r0[r * n + c] = v;
     }
     if (c >= r) put_packed(r0pk, np, n, r, c, v);
@@ -198,7 +212,12 @@ __global__ __launch_bounds__(256) void finalize_r0_kernel(const double* __restri
 }
 
 hipError_t launch_finalize_r0(const double* rin, int n, int np, int32_t* info, double* r0, double* r0pk, hipStream_t s) {
-  hipLaunchKernelGGL(finalize_r0_kernel, dim3(1), dim3(256), 0, s, rin, n, np, info, r0, r0pk);
+  hipLaunchKernelGGL(finalize_r0_kernel<double>, dim3(1), dim3(256), 0, s, rin, n, np, info, r0, r0pk);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_r0(const float* rin, int n, int np, int32_t* info, double* r0, double* r0pk, hipStream_t s) {
+  hipLaunchKernelGGL(finalize_r0_kernel<float>, dim3(1), dim3(256), 0, s, rin, n, np, info, r0, r0pk);
   return hipGetLastError();
 }
 

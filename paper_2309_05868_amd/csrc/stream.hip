@@ -8,9 +8,10 @@
 //                    G += X^T X is accumulated with v_mfma_f64_16x16x4f64 on the upper 16x16
 //                    blocks.  Each workgroup sums its waves in fixed order and writes one
 //                    partial; the workgroup count is fixed, so the summation order is too.
-//  final_kernel      Q = Q0 R1^{-1} (Algorithm 2, step 3 on Q0): recomputes the same Q0 row with
+//  final_mfma_kernel Q = Q0 R1^{-1} (Algorithm 2, step 3 on Q0): recomputes the same Q0 row with
 //                    the same device function (bitwise identical to the Gram pass: explicit
-//                    FMAs, no implicit contraction) and solves with R1 by substitution.
+//                    FMAs, no implicit contraction) and applies R1^{-1} on the matrix cores.
+//  final_kernel      Q0 = V R0^{-1} alone (one substitution), for the paths that need only that.
 //
 // Rows are padded to NP columns; the padded R has an identity block, so padded columns stay
 // zero and contribute nothing.
@@ -36,13 +37,13 @@ __device__ __forceinline__ int opaque_zero(double after) {
 //   Rpk = [1/R00, R01, ..., R0,NP-1, 1/R11, R12, ..., 1/R(NP-1)(NP-1)].
 // Column-oriented forward substitution: x_k = v_k * (1/R_kk), then v_j -= x_k R_kj (j > k),
 // k ascending.  The coefficients are uniform across the wave and are streamed into scalar
-// registers eight at a time, two chunks ahead of use; a scheduling barrier per chunk keeps
-// the compiler from hoisting all of them at once.
-template <int NP>
+// registers eight at a time, PD chunks ahead of use; a scheduling barrier per chunk keeps
+// the compiler from hoisting all of them at once.  PD changes only the load schedule, never
+// the arithmetic, so every caller gets bitwise the same x.
+template <int NP, int PD = 4>
 __device__ __forceinline__ void rowsolve(double (&x)[NP], const double* __restrict__ Rpk) {
   constexpr int NV = NP * (NP + 1) / 2;
   constexpr int NCH = (NV + 7) / 8;
-  constexpr int PD = 2;
   double buf[PD + 1][8];
 #pragma unroll
   for (int ch = 0; ch < PD; ++ch) {
@@ -220,6 +221,178 @@ __global__ __launch_bounds__(NW * kWave) void final_kernel(const double* __restr
   }
 }
 
+// Upper 16x16 block (a, b), a <= b, of an NB x NB block grid, numbered row by row.
+__device__ __forceinline__ int upper_blk(int a, int b, int nb) { return a * nb - a * (a - 1) / 2 + (b - a); }
+
+// Q = (V R0^{-1}) R1^{-1} with the second step on the matrix cores.  R1 is the Cholesky factor
+// of the Gram matrix of Q0, whose condition number is that of Q0, O(1) (Section 4's remark on
+// kappa of randQR's Q); its inverse is formed accurately and applied as a product, while the
+// solve with the ill-conditioned R0 stays a row-wise substitution (Section 5.2).
+//   * wave 0 of each workgroup forms row i of R1^{-1} in lane i by the same substitution
+//     (x R1 = e_i) and stores its upper 16x16 blocks in LDS;
+//   * per tile of 64 rows: x = v R0^{-1} (lane = row), then 16 rows at a time go through LDS
+//     into MFMA operands, Q[16 rows] = X[16 rows] R1^{-1} on v_mfma_f64_16x16x4f64
+//     (upper blocks only), written straight from the accumulators.
+// Only R0 streams through the scalar data cache (R0 and R1 together would not fit it).
+template <int NP, bool FULL, int NW>
+__global__ __launch_bounds__(NW * kWave) void final_mfma_kernel(const double* __restrict__ V, int64_t m, int n, int64_t ldv,
+                                                               const double* __restrict__ R0pk, const double* __restrict__ R1pk,
+                                                               const int32_t* __restrict__ info, double* __restrict__ Q,
+                                                               int64_t ldq) {
+  constexpr int NB = NP / 16;
+  constexpr int NBU = NB * (NB + 1) / 2;
+  __shared__ double rib[NBU * 256];
+  __shared__ double st[NW][16][NP + 1];
+  if (info[0] != 0) return;
+  const int wave = threadIdx.x / kWave, lane = lane_id();
+  const int li = lane & 15, lq = lane >> 4;
+  if (wave == 0) {
+    double x[NP];
+#pragma unroll
+    for (int c = 0; c < NP; ++c) x[c] = (c == lane) ? 1.0 : 0.0;
+    rowsolve<NP>(x, R1pk);
+    if (lane < NP) {
+      const int a = lane / 16;
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) {
+        if (cb >= a) {
+#pragma unroll
+          for (int j = 0; j < 16; ++j) rib[upper_blk(a, cb, NB) * 256 + (lane & 15) * 16 + j] = x[16 * cb + j];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  double (*s)[NP + 1] = st[wave];
+  const int64_t ntiles = (m + kWave - 1) / kWave;
+  for (int64_t t = (int64_t)blockIdx.x * NW + wave; t < ntiles; t += (int64_t)gridDim.x * NW) {
+    const int64_t row = t * kWave + lane;
+    double x[NP];
+    load_row<NP, FULL>(x, V, row, m, n, ldv);
+    rowsolve<NP>(x, R0pk);
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      if (lq == rb) {
+#pragma unroll
+        for (int c = 0; c < NP; ++c) s[li][c] = x[c];
+      }
+      wave_lds_sync();
+      d4 acc[NB];
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < NP / 4; ++k) {
+        const double a = s[li][4 * k + lq];
+#pragma unroll
+        for (int cb = k / 4; cb < NB; ++cb)
+          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, rib[upper_blk(k / 4, cb, NB) * 256 + (4 * (k % 4) + lq) * 16 + li],
+                                                         acc[cb], 0, 0, 0);
+      }
+      wave_lds_sync();
+      // accumulator element e of lane l holds row l/16 + 4e, column l%16 of the 16 x 16 block
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) {
+        const int col = 16 * cb + li;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t r = t * kWave + 16 * rb + lq + 4 * e;
+          if (r < m && (FULL || col < n)) Q[r * ldq + col] = acc[cb][e];
+        }
+      }
+    }
+  }
+}
+
+// 65..128 columns: a row does not fit a lane's registers next to the solve's working set, so
+// x R = v runs as a 2 x 2 block substitution over 64-column halves (Section 5.2's row-wise
+// substitution on the diagonal blocks, a product for the coupling block):
+//     x_lo = v_lo R00^{-1}                  final_kernel<64>, written to the output row
+//     x_hi = (v_hi - x_lo R01) R11^{-1}     solve_hi_kernel
+// The factor is in the blocked packed format [R00 packed | R01 dense row-major | R11 packed]
+// (2080 + 4096 + 2080 doubles).  In solve_hi_kernel the coupling product runs on the matrix
+// cores: R01 sits in LDS, x_lo is read back from the output rows as MFMA operands (16 rows x 4
+// columns per K-step), and each 16-row block of x_lo R01 goes through LDS to the lanes that own
+// those rows.  Only R11 streams through the scalar data cache.
+template <bool FULL, int NW>
+__global__ __launch_bounds__(NW * kWave) void solve_hi_kernel(const double* in, int64_t m, int n, int64_t ldin,
+                                                             const double* __restrict__ Rbk, const int32_t* __restrict__ info,
+                                                             double* out, int64_t ldout) {
+  constexpr int H = 64, PK = H * (H + 1) / 2;
+  __shared__ double r01[H][H + 1];
+  __shared__ double ust[NW][16][H + 1];
+  if (info[0] != 0) return;
+  for (int i = threadIdx.x; i < H * H; i += NW * kWave) r01[i / H][i % H] = Rbk[PK + i];
+  __syncthreads();
+  const int wave = threadIdx.x / kWave, lane = lane_id();
+  const int li = lane & 15, lq = lane >> 4;
+  const int nh = n - H;
+  double (*u)[H + 1] = ust[wave];
+  const int64_t ntiles = (m + kWave - 1) / kWave;
+  for (int64_t t = (int64_t)blockIdx.x * NW + wave; t < ntiles; t += (int64_t)gridDim.x * NW) {
+    const int64_t row = t * kWave + lane;
+    double x[H];
+    if (row < m) {
+      const double* src = in + row * ldin + H;
+      if constexpr (FULL) {
+        const double2* s2 = reinterpret_cast<const double2*>(src);
+#pragma unroll
+        for (int c = 0; c < H / 2; ++c) {
+          const double2 v = s2[c];
+          x[2 * c] = v.x;
+          x[2 * c + 1] = v.y;
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < H; ++c) x[c] = c < nh ? src[c] : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < H; ++c) x[c] = 0.0;
+    }
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      const int64_t arow = t * kWave + 16 * rb + li;
+      const double* xl = out + arow * ldout;
+      double a[16];
+#pragma unroll
+      for (int ks = 0; ks < 16; ++ks) a[ks] = arow < m ? xl[4 * ks + lq] : 0.0;
+      d4 acc[4];
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < 16; ++ks) {
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], r01[4 * ks + lq][16 * cb + li], acc[cb], 0, 0, 0);
+      }
+      // element e of lane l: row 16 rb + l/16 + 4e, column 16 cb + l%16 of x_lo R01
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) u[lq + 4 * e][16 * cb + li] = acc[cb][e];
+      wave_lds_sync();
+      if (lq == rb) {
+#pragma unroll
+        for (int c = 0; c < H; ++c) x[c] -= u[li][c];
+      }
+      wave_lds_sync();
+    }
+    rowsolve<H>(x, Rbk + PK + H * H);
+    if (row < m) {
+      double* dst = out + row * ldout + H;
+      if constexpr (FULL) {
+        double2* d2 = reinterpret_cast<double2*>(dst);
+#pragma unroll
+        for (int c = 0; c < H / 2; ++c) d2[c] = double2{x[2 * c], x[2 * c + 1]};
+      } else {
+#pragma unroll
+        for (int c = 0; c < H; ++c)
+          if (c < nh) dst[c] = x[c];
+      }
+    }
+  }
+}
+
 static bool full_rows(int np, int n, const void* a, int64_t lda, const void* b, int64_t ldb) {
   const bool al = (reinterpret_cast<uintptr_t>(a) % 16 == 0) && (lda % 2 == 0);
   const bool bl = b == nullptr || ((reinterpret_cast<uintptr_t>(b) % 16 == 0) && (ldb % 2 == 0));
@@ -259,18 +432,34 @@ hipError_t launch_final(int np, bool apply_r1, const double* V, int64_t m, int n
                         const double* r1pk, const int32_t* info, double* Q, int64_t ldq, hipStream_t s) {
   if (m <= 0) return hipSuccess;
   const bool full = full_rows(np, n, V, ldv, Q, ldq);
-  // waves per workgroup = waves that fit one CU at this kernel's register use (one workgroup per CU)
+  const int64_t tiles = (m + kWave - 1) / kWave;
+  if (apply_r1) {
+    // eight waves per workgroup, about two workgroups per CU over the whole pass
+    constexpr int NW = 8;
+    int64_t g = (tiles + NW - 1) / NW;
+    if (g > 2 * final_grid()) g = 2 * final_grid();
+    const dim3 grid((unsigned)g), block(NW * kWave);
+#define RCQR_FINAL_MFMA(NPV)                                                                                                  \
+  if (full)                                                                                                                   \
+    hipLaunchKernelGGL((final_mfma_kernel<NPV, true, NW>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq);      \
+  else                                                                                                                        \
+    hipLaunchKernelGGL((final_mfma_kernel<NPV, false, NW>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq);
+    switch (np) {
+      case 16: RCQR_FINAL_MFMA(16) break;
+      case 32: RCQR_FINAL_MFMA(32) break;
+      case 64: RCQR_FINAL_MFMA(64) break;
+      default: return hipErrorInvalidValue;
+    }
+#undef RCQR_FINAL_MFMA
+    return hipGetLastError();
+  }
+  // one factor: Q0 = V R0^{-1} only (persistent, one workgroup per CU)
 #define RCQR_FINAL(NPV, NWV)                                                                                                    \
   {                                                                                                                             \
-    const int64_t tiles = (m + kWave - 1) / kWave;                                                                              \
     int64_t g = (tiles + NWV - 1) / NWV;                                                                                        \
     if (g > final_grid()) g = final_grid();                                                                                     \
     const dim3 grid((unsigned)g), block(NWV * kWave);                                                                           \
-    if (apply_r1 && full)                                                                                                       \
-      hipLaunchKernelGGL((final_kernel<NPV, true, true, NWV>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq);     \
-    else if (apply_r1)                                                                                                          \
-      hipLaunchKernelGGL((final_kernel<NPV, true, false, NWV>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq);    \
-    else if (full)                                                                                                              \
+    if (full)                                                                                                                   \
       hipLaunchKernelGGL((final_kernel<NPV, false, true, NWV>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq);    \
     else                                                                                                                        \
       hipLaunchKernelGGL((final_kernel<NPV, false, false, NWV>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq);   \
@@ -282,6 +471,26 @@ hipError_t launch_final(int np, bool apply_r1, const double* V, int64_t m, int n
     default: return hipErrorInvalidValue;
   }
 #undef RCQR_FINAL
+  return hipGetLastError();
+}
+
+hipError_t launch_solve128(const double* in, int64_t m, int n, int64_t ldin, const double* rbk, const int32_t* info, double* out,
+                           int64_t ldout, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  if (n <= 64 || n > 128) return hipErrorInvalidValue;
+  // x_lo = v_lo R00^{-1} into the output's first 64 columns (R00 packed leads the blocked format)
+  const hipError_t e = launch_final(64, false, in, m, 64, ldin, rbk, rbk, info, out, ldout, s);
+  if (e != hipSuccess) return e;
+  constexpr int NW = 8;
+  const int64_t tiles = (m + kWave - 1) / kWave;
+  int64_t g = (tiles + NW - 1) / NW;
+  if (g > 2 * final_grid()) g = 2 * final_grid();
+  const dim3 grid((unsigned)g), block(NW * kWave);
+  const bool full = n == 128 && full_rows(64, 64, in, ldin, out, ldout);
+  if (full)
+    hipLaunchKernelGGL((solve_hi_kernel<true, NW>), grid, block, 0, s, in, m, n, ldin, rbk, info, out, ldout);
+  else
+    hipLaunchKernelGGL((solve_hi_kernel<false, NW>), grid, block, 0, s, in, m, n, ldin, rbk, info, out, ldout);
   return hipGetLastError();
 }
 

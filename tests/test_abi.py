@@ -41,15 +41,19 @@ def test_workspace_bytes_and_shape_checks(lib):
     assert rc.workspace_bytes(10_000, 100, 20_000, 400) > 0
     assert rc.workspace_bytes(10_000, 129, 40_000, 600) == 0  # n beyond the kernels
     assert rc.workspace_bytes(2**31, 8, 128, 32) == 0   # row index must fit 31 bits
+    for flags in (rc.FLAG_SKETCH_FP32, rc.FLAG_SKETCH_FP32 | rc.FLAG_GEMM_BF16, rc.FLAG_REORTH, 7):
+        assert rc.workspace_bytes(10_000, 16, 512, 64, flags) == ws
+    assert rc.workspace_bytes(10_000, 16, 512, 64, 8) == 0
+    assert rc.workspace_bytes(10_000, 16, 512, 64, rc.FLAG_GEMM_BF16) == 0
 
 
 def test_status_strings_and_phase_names(lib):
     assert rc.status_string(rc.OK) == "ok"
     assert "Cholesky" in rc.status_string(rc.E_CHOL)
     assert "diagonal" in rc.status_string(rc.E_RANK)
-    names = [lib.rcqr_phase_name(i).decode() for i in range(6)]
-    assert names == ["countsketch", "gaussian", "householder", "trsm_gram", "cholesky", "final"]
-    assert lib.rcqr_phase_name(6).decode() == "?"
+    names = [lib.rcqr_phase_name(i).decode() for i in range(7)]
+    assert names == ["countsketch", "gaussian", "householder", "trsm_gram", "cholesky", "reorth", "final"]
+    assert lib.rcqr_phase_name(7).decode() == "?"
 
 
 def test_plan_rejects_bad_arguments_on_host(lib):
@@ -58,7 +62,9 @@ def test_plan_rejects_bad_arguments_on_host(lib):
     assert lib.rcqr_plan(ctypes.byref(h), 1000, 16, 512, 64, 0, 0, None, 0, None) == rc.E_INVALID
     assert lib.rcqr_plan(ctypes.byref(h), 1000, 16, 8, 64, 0, 0, ctypes.c_void_p(256), 1 << 30, None) == rc.E_INVALID
     assert lib.rcqr_plan(ctypes.byref(h), 1000, 129, 40_000, 600, 0, 0, ctypes.c_void_p(256), 1 << 30, None) == rc.E_UNSUPPORTED
-    assert lib.rcqr_plan(ctypes.byref(h), 1000, 16, 512, 64, 0, 1, ctypes.c_void_p(256), 1 << 30, None) == rc.E_INVALID
+    assert lib.rcqr_plan(ctypes.byref(h), 1000, 16, 512, 64, 0, 8, ctypes.c_void_p(256), 1 << 30, None) == rc.E_INVALID
+    assert lib.rcqr_plan(ctypes.byref(h), 1000, 16, 512, 64, 0, rc.FLAG_GEMM_BF16, ctypes.c_void_p(256), 1 << 30,
+                         None) == rc.E_INVALID  # BF16 product needs the FP32 sketch
     assert lib.rcqr_plan(ctypes.byref(h), 1000, 16, 512, 64, 0, 0, ctypes.c_void_p(8), 1 << 30, None) == rc.E_INVALID
     assert lib.rcqr_plan(None, 1000, 16, 512, 64, 0, 0, ctypes.c_void_p(256), 1 << 30, None) == rc.E_INVALID
     # a plan with a fake (never touched) workspace pointer: I/O argument checks are host-side

@@ -1,0 +1,182 @@
+"""Single-precision preconditioner variants (plan flags) against the FP64 oracle.
+
+RCQR_FLAG_SKETCH_FP32 computes W1 = S1 V, W = S2 W1 and the Householder R0 in FP32 (the Gaussian
+product on the FP32 matrix cores), RCQR_FLAG_GEMM_BF16 rounds the product's operands to BF16,
+RCQR_FLAG_REORTH adds a second Cholesky QR.  Everything after R0 stays FP64, and Q, R are the
+unique thin QR factors of V whatever the preconditioner (Algorithm 3's result does not depend on
+the sketch), so the final checks are the FP64 ones.
+
+Bounds (u32 = 2^-24):
+  * W1 of integer-valued V (bucket sums < 2^24): bit-exact against the exact oracle sum;
+  * W1 of real V, entrywise: |dW1| <= (cnt_b + 600) u32 sum_{i in b} |V[i, c]| (rounding of every
+    V entry to FP32 plus any summation order of the bucket's cnt_b terms, the LDS path's wave
+    copies and up to 512 partials);
+  * W against the same product done in FP64 from the device's FP32 (or BF16-rounded) operands,
+    entrywise: |dW| <= (s1 + 64) u32 (|S2| |W1|) (FP32 accumulation, any order);
+  * R0: Householder backward error ||R0^T R0 - W^T W||_F <= 30 n u32 ||W||_F^2;
+  * Q, R at kappa <= 1e6: ||dR||_F / ||R||_F <= 1e-10 against LAPACK, ||I - Q^T Q||_F and the
+    residual <= 10 n u (u = 2^-52).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import sketch as osk
+from oracle.countsketch import apply_countsketch
+from oracle.rand_cholqr import U_PAPER
+
+pytestmark = pytest.mark.gpu
+
+rc = pytest.importorskip("paper_2309_05868_amd")
+
+U32 = 2.0 ** -24
+FP32 = 1
+BF16 = 1 | 2
+REORTH = 4
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def lapack_r(A):
+    R = np.linalg.qr(A, mode="r")
+    return R * np.sign(np.diag(R))[:, None]
+
+
+def to_bf16(x):
+    """Round float32 values to bfloat16 (nearest, ties to even), returned as float32."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32)
+
+
+def errors(V, Q, R):
+    n = V.shape[1]
+    return np.linalg.norm(np.eye(n) - Q.T @ Q), np.linalg.norm(V - Q @ R) / np.linalg.norm(V)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rc.lib()
+
+
+@pytest.mark.parametrize("m,n,s1", [(10_000, 16, 256), (50_000, 64, 8192), (20_000, 128, 1000)])
+def test_fp32_countsketch_integer_bit_exact(m, n, s1):
+    say("fp32 countsketch int", m, n, s1)
+    V = synth.make_int_V(m, n, seed=m + n)
+    with rc.Plan(m, n, s1, max(n, 16), seed=5, flags=FP32) as p:
+        p.factor(dev(V), check=False)
+        W1 = host(p.intermediates()["W1"])
+    b, g = osk.countsketch_hash(m, s1, 5)
+    np.testing.assert_array_equal(W1, apply_countsketch(V, b, g, s1))
+
+
+@pytest.mark.parametrize("flags", [FP32, BF16])
+@pytest.mark.parametrize("m,n,s1,s2", [(10_000, 16, 512, 64), (40_000, 64, 8192, 256), (9999, 50, 700, 100),
+                                       (20_000, 128, 4096, 512)])
+def test_fp32_sketch_intermediates(flags, m, n, s1, s2):
+    say("fp32 sketch", flags, m, n, s1, s2)
+    seed = 21
+    V = synth.make_V(m, n, 1e5, seed=seed)
+    with rc.Plan(m, n, s1, s2, seed, flags=flags) as p:
+        p.factor(dev(V))
+        it = {k: host(v) for k, v in p.intermediates().items()}
+    b, g = osk.countsketch_hash(m, s1, seed)
+    W1_exact = apply_countsketch(V, b, g, s1)
+    absum = apply_countsketch(np.abs(V), b, np.ones_like(g), s1)
+    cnt = np.bincount(b, minlength=s1)[:, None].astype(np.float64)
+    assert np.all(np.abs(it["W1"] - W1_exact) <= (cnt + 600) * U32 * absum)
+    assert np.array_equal(it["W1"], it["W1"].astype(np.float32).astype(np.float64))
+    S2 = osk.gaussian_sketch(s2, s1, seed).astype(np.float32)
+    W1 = it["W1"].astype(np.float32)
+    if flags & 2:
+        S2, W1 = to_bf16(S2), to_bf16(W1)
+    S2, W1 = S2.astype(np.float64), W1.astype(np.float64)
+    Wref = S2 @ W1
+    assert np.all(np.abs(it["W"] - Wref) <= (s1 + 64) * U32 * (np.abs(S2) @ np.abs(W1)))
+    assert rel(it["W"], Wref) <= 2e-5
+    W = it["W"]
+    R0 = it["R0"]
+    assert np.all(np.diag(R0) > 0) and np.all(np.tril(R0, -1) == 0)
+    assert np.linalg.norm(R0.T @ R0 - W.T @ W) <= 30 * n * U32 * np.linalg.norm(W) ** 2
+
+
+# BF16 operands perturb W by about 2^-9 relative, so kappa(Q0) ~ 2^-9 kappa(V): at kappa 1e5 the
+# BF16 product needs the second Cholesky QR; the FP32 sketch alone does not.
+@pytest.mark.parametrize("flags", [FP32, FP32 | REORTH, BF16 | REORTH, REORTH])
+@pytest.mark.parametrize("m,n,s1,s2", [(20_000, 16, 512, 64), (30_000, 64, 8192, 256), (20_000, 128, 4096, 512)])
+def test_variants_reach_the_fp64_result(flags, m, n, s1, s2):
+    say("variant", flags, m, n)
+    V, (_, sig, W) = synth.make_V(m, n, 1e5, seed=31, return_factors=True)
+    with rc.Plan(m, n, s1, s2, seed=31, flags=flags) as p:
+        Q, R = p.factor(dev(V))
+    Q, R = host(Q), host(R)
+    tgt = 10 * n * U_PAPER
+    orth, res = errors(V, Q, R)
+    assert orth <= tgt and res <= tgt
+    assert rel(R, lapack_r(sig[:, None] * W.T)) <= 1e-10
+    assert np.all(np.diag(R) > 0) and np.all(np.tril(R, -1) == 0)
+
+
+@pytest.mark.parametrize("n,s1,s2", [(16, 512, 64), (64, 8192, 256)])
+def test_fp32_with_reorth_at_large_kappa(n, s1, s2):
+    # the FP32 preconditioner leaves kappa(Q0) ~ u32 kappa(V); one more Cholesky QR restores O(u)
+    m = 30_000
+    tgt = 10 * n * U_PAPER
+    for kappa in (1e10, 1e12):
+        say("fp32+reorth", n, kappa)
+        V = synth.make_V(m, n, kappa, seed=41)
+        with rc.Plan(m, n, s1, s2, seed=41, flags=FP32 | REORTH) as p:
+            Q, R = p.factor(dev(V))
+        orth, res = errors(V, host(Q), host(R))
+        say(f"  orth {orth:.2e} res {res:.2e} target {tgt:.2e}")
+        assert orth <= tgt and res <= tgt
+
+
+def test_fp64_reorth_at_kappa_1e15():
+    m, n, s1, s2 = 30_000, 64, 8192, 256
+    V = synth.make_V(m, n, 1e15, seed=42)
+    with rc.Plan(m, n, s1, s2, seed=42, flags=REORTH) as p:
+        Q, R = p.factor(dev(V))
+        R2 = host(p.intermediates()["R1"])
+    orth, res = errors(V, host(Q), host(R))
+    tgt = 10 * n * U_PAPER
+    assert orth <= tgt and res <= tgt
+    # Q1 = V (R1 R0)^{-1} is off orthogonality by O(n u kappa(V)) (Section 5.3's remark on
+    # V R^{-1}), so its R2 is well conditioned but not the identity
+    assert np.linalg.cond(R2) <= 100
+
+
+def test_fp32_errors_reported_at_kappa_1e14():
+    # outside 1/u32 the single-precision preconditioner alone is not expected to reach 10 n u;
+    # the numbers are printed, the statuses must be well-formed
+    m, n, s1, s2 = 30_000, 32, 2048, 128
+    V = synth.make_V(m, n, 1e14, seed=43)
+    for flags in (FP32, BF16, FP32 | REORTH, BF16 | REORTH):
+        with rc.Plan(m, n, s1, s2, seed=43, flags=flags) as p:
+            Q, R = p.factor(dev(V), check=False)
+            st, col = p.info()
+        assert st in (rc.OK, rc.E_CHOL, rc.E_RANK)
+        if st == rc.OK:
+            orth, res = errors(V, host(Q), host(R))
+            say(f"flags {flags}: orth {orth:.2e} res {res:.2e}")
+        else:
+            say(f"flags {flags}: status {st} column {col}")

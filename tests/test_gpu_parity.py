@@ -111,8 +111,11 @@ def test_sketches_R0_and_R_match_oracle(m, n, s1, s2, kappa):
     assert rel(it["W1"], o["W1"]) <= 1e-13
     assert rel(it["W"], o["W"]) <= 1e-13
     assert rel(it["R0"], o["R0"]) <= 1e-10
-    assert rel(it["R1"], o["R1"]) <= 1e-10
-    assert rel(np.triu(it["G"]), np.triu(o["G"])) <= 1e-10
+    # G and R1 are built from Q0, whose forward error is O(kappa u) (only row-wise backward
+    # stability holds, Section 5.2): same kappa scaling as the Q comparison below
+    tol_q0 = 1e-10 * max(1.0, kappa / 1e4)
+    assert rel(it["R1"], o["R1"]) <= tol_q0
+    assert rel(np.triu(it["G"]), np.triu(o["G"])) <= tol_q0
     assert rel(R, o["R"]) <= 1e-10
     assert np.all(np.tril(R, -1) == 0) and np.all(np.diag(R) > 0)
     Rref = lapack_r(sig[:, None] * W.T)
