@@ -15,6 +15,7 @@ timed region), and the CPU oracle timed on a bounded sample of the same workload
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-comparators]
   python bench.py --workload mixed     # precision variants, m = 4e6, n = 128, kappa = 1e14
+  python bench.py --workload serve     # 4096 requests, continuous batching vs one at a time
 """
 
 import argparse
@@ -36,6 +37,10 @@ U_PAPER = 2.0 ** -52
 WORKLOAD = dict(m=2_000_000, n=64, kappa=1e12, s1=8192, s2=256, seed=1)
 # single-precision preconditioner against plain FP64 on the same GPU
 MIXED_WORKLOAD = dict(m=4_000_000, n=128, kappa=1e14, s1=32768, s2=512, seed=3)
+# serving: Poisson arrivals, log-uniform m, uniform n, log-uniform kappa (snapped to a bank of bases)
+SERVE_WORKLOAD = dict(count=4096, rate_per_s=2000.0, seed=4, m_range=(1e4, 2e6), n_choices=(8, 16, 32, 64, 128),
+                      kappa_range=(1e2, 1e15))
+SERVE_KAPPA_BANK = [10.0 ** e for e in (2.0, 4.6, 7.2, 9.8, 12.4, 15.0)]
 MIXED_VARIANTS = [("fp64", 0), ("fp32_sketch", 1), ("bf16_gemm", 3), ("fp64_reorth", 4), ("fp32_sketch_reorth", 5),
                   ("bf16_gemm_reorth", 7)]
 
@@ -169,6 +174,76 @@ def mixed_variants(args):
     print(json.dumps(line), flush=True)
 
 
+def serve_workload(args):
+    """Continuous batching over several streams against one request at a time (per-request plain
+    launches), on the same request list: completed QR/s and p50 / p99 latency."""
+    import numpy as np
+    import torch
+
+    import paper_2309_05868_amd as rc
+    import synth
+    from paper_2309_05868_amd import serve as srv
+
+    wl = SERVE_WORKLOAD
+    dev = torch.device("cuda:0")
+    reqs = synth.make_requests(wl["count"], wl["seed"], rate_per_s=wl["rate_per_s"], m_range=wl["m_range"],
+                               n_choices=wl["n_choices"], kappa_range=wl["kappa_range"])
+    m_max = max(r["m"] for r in reqs)
+    bank = {}
+    for n in wl["n_choices"]:
+        log(f"bench: serving bank n={n}")
+        U, _, W = synth.make_factors(m_max, n, 1.0, seed=5000 + n)
+        Ud, Wt = torch.from_numpy(U).to(dev), torch.from_numpy(np.ascontiguousarray(W.T)).to(dev)
+        del U
+        for kb in SERVE_KAPPA_BANK:
+            sig = torch.from_numpy(synth.singular_values(n, kb)).to(dev)
+            bank[(n, kb)] = (Ud * sig) @ Wt
+        del Ud
+    log_bank = np.log(np.asarray(SERVE_KAPPA_BANK))
+
+    def nearest(kappa):
+        return SERVE_KAPPA_BANK[int(np.argmin(np.abs(log_bank - np.log(kappa))))]
+
+    def get_V(r):
+        return bank[(r["n"], nearest(r["kappa"]))][: r["m"]]
+
+    torch.cuda.synchronize()
+    warm = [dict(r, arrival_s=0.0) for r in reqs[:16]]
+    srv.serve(warm, get_V, slots=4, budget_bytes=args.serve_budget_gb << 30)
+    out = {}
+    for name, slots in (("continuous_batching", args.serve_slots), ("one_at_a_time", 1)):
+        log(f"bench: serving {len(reqs)} requests, {name} ({slots} stream(s))")
+        run, summary, _ = srv.serve(reqs, get_V, slots=slots, budget_bytes=args.serve_budget_gb << 30)
+        summary["slots"] = slots
+        out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summary.items()}
+    # accuracy of a sample of requests (each factored alone)
+    rng = np.random.Generator(np.random.PCG64(9))
+    worst = 0.0
+    for i in rng.choice(len(reqs), size=32, replace=False):
+        r = reqs[int(i)]
+        V = get_V(r)
+        with rc.Plan(r["m"], r["n"], r["s1"], r["s2"], r["seed"], device=dev) as p:
+            Q, R = p.factor(V)
+        n = r["n"]
+        eye = torch.eye(n, dtype=torch.float64, device=dev)
+        orth = torch.linalg.norm(eye - gram_accurate(Q)).item()
+        res = (torch.linalg.norm(V - Q @ R) / torch.linalg.norm(V)).item()
+        worst = max(worst, orth / (10 * n * U_PAPER), res / (10 * n * U_PAPER))
+    line = {
+        "metric": METRIC, "value": out["continuous_batching"].get("qr_per_s"), "unit": "QR/s", "n_gpus": 1,
+        "steps": len(reqs), "warmup": len(warm), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"rand_cholQR serving: {wl['count']} requests, Poisson {wl['rate_per_s']:.0f}/s, "
+                               f"m log-uniform [{wl['m_range'][0]:.0e}, {wl['m_range'][1]:.0e}], n in {list(wl['n_choices'])}, "
+                               f"kappa log-uniform [{wl['kappa_range'][0]:.0e}, {wl['kappa_range'][1]:.0e}], s1 = 2n^2, s2 = 4n"},
+        "p50_ms": out["continuous_batching"].get("p50_ms"), "p99_ms": out["continuous_batching"].get("p99_ms"),
+        "modes": out, "sample_worst_error_over_10nu": worst,
+        "note": "V = leading m rows of a resident base with the nearest of 6 log-spaced kappa values; "
+                "latency = device completion - arrival",
+    }
+    print(json.dumps(line), flush=True)
+
+
 def cpu_baseline(wl, sample_rows):
     """The oracle as it stands, single-threaded, on a row-scaled sample of the workload."""
     from threadpoolctl import threadpool_limits
@@ -200,8 +275,11 @@ def main():
     ap.add_argument("--no-comparators", action="store_true", help="skip timing cholQR2 and sCholQR3 on the same V")
     ap.add_argument("--comparator-steps", type=int, default=5)
     ap.add_argument("--cpu-sample-rows", type=int, default=100_000)
-    ap.add_argument("--workload", choices=["default", "mixed"], default="default",
-                    help="mixed: FP32/BF16 preconditioner variants against FP64 at m=4e6, n=128, kappa=1e14")
+    ap.add_argument("--workload", choices=["default", "mixed", "serve"], default="default",
+                    help="mixed: FP32/BF16 preconditioner variants against FP64 at m=4e6, n=128, kappa=1e14; "
+                         "serve: continuous batching of 4096 Poisson-arriving requests")
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-budget-gb", type=int, default=64)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device-to-device copy of V's size (HBM counter calibration)")
     args = ap.parse_args()
@@ -231,6 +309,9 @@ def main():
         build.build()
     if args.workload == "mixed":
         mixed_variants(args)
+        return
+    if args.workload == "serve":
+        serve_workload(args)
         return
     wl = WORKLOAD
     m, n = wl["m"], wl["n"]

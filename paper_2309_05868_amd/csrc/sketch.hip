@@ -98,12 +98,18 @@ hipError_t launch_hash_hist(int64_t m, int64_t s1, uint64_t seed, int nchunk, ui
 // counts[b] <- total rows of bucket b.
 __global__ __launch_bounds__(256) void hist_colscan_kernel(int nchunk, int64_t s1, uint32_t* __restrict__ hist, uint32_t* __restrict__ counts) {
   for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < s1; b += (int64_t)gridDim.x * blockDim.x) {
+    // the loads of a batch are independent: issue them together, then scan and store
+    constexpr int BATCH = 16;
     uint32_t run = 0;
-    for (int c = 0; c < nchunk; ++c) {
-      uint32_t* h = hist + (int64_t)c * s1 + b;
-      const uint32_t v = *h;
-      *h = run;
-      run += v;
+    for (int c0 = 0; c0 < nchunk; c0 += BATCH) {
+      uint32_t v[BATCH];
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) v[u] = (c0 + u < nchunk) ? hist[(int64_t)(c0 + u) * s1 + b] : 0u;
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        if (c0 + u < nchunk) hist[(int64_t)(c0 + u) * s1 + b] = run;
+        run += v[u];
+      }
     }
     counts[b] = run;
   }
@@ -236,7 +242,7 @@ __device__ __forceinline__ void gather_rows(const uint32_t* keys, int cnt, const
   const int g = NPL >= 64 ? 0 : lane / NPL;
   const int c = NPL >= 64 ? lane : lane % NPL;
   int e = g;
-  // eight rows in flight, added in entry order
+  // eight rows in flight per lane group, added in entry order
   constexpr int U = 8;
   for (; e + (U - 1) * G < cnt; e += U * G) {
     uint32_t kk[U];

@@ -18,111 +18,120 @@
 namespace rcqr {
 
 // ------------------------------------------------------------------------------------------
-// Householder QR of a p x n block (p <= 256), matrix held in registers.
-// Thread layout: column c = t / TPC, row group rg = t % TPC; a thread owns rows rg + TPC*e.
-// The TPC threads of a column are consecutive lanes of one wave, so column reductions are wave
-// shuffles, and the CPW = 64 / TPC columns of a wave form a panel.  Panel by panel: the owning
-// wave computes the panel's reflectors one after another (each applied at once to the panel's
-// later columns), with only wave-level LDS ordering; after one workgroup barrier every later
-// column applies the panel's reflectors in order.  Reflector j maps column j's x = A[j:, j] to
-// beta e1 with beta = -sign(x0) ||x||, H = I - tau v v^T, v[0] = 1.
+// Householder QR of a p x n block (p <= 256, n <= 128), R factor only, matrix in registers.
+// Sixteen waves; wave w owns columns w, w + 16, ... (NC of them) and lane l owns rows l, l + 64,
+// l + 128, l + 192, so every column reduction is one wave's butterfly.  Reflector j is built by
+// the owner of column j: it maps x = A[j:, j] to beta e1, beta = -sign(x0) ||x||,
+// H = I - tau v v^T with v[0] = 1; v and tau go through LDS (double-buffered, so one workgroup
+// barrier per reflector) and every wave applies H to its columns right of j.
 // ------------------------------------------------------------------------------------------
 constexpr int kQrMaxRows = 256;
+constexpr int kQrWaves = 16;
 
-template <int TPC, class T>
-__device__ __forceinline__ T group_sum(T v) {
-#pragma unroll
-  for (int off = TPC / 2; off > 0; off >>= 1) v += shfl_xor_d(v, off);
-  return v;
-}
 
-template <int NPAD, int TPC, class T>
-__global__ __launch_bounds__(NPAD * TPC) void qr_block_kernel(const T* __restrict__ in, int64_t ldin, int64_t p_total,
-                                                             int64_t rows_per_block, int n, T* __restrict__ out) {
-  static_assert(TPC <= 64 && (64 % TPC) == 0, "a column's threads must sit in one wave");
-  constexpr int EPT = kQrMaxRows / TPC;
-  constexpr int CPW = 64 / TPC;  // columns per wave = panel width
-  __shared__ T vbuf[2][CPW][kQrMaxRows];
-  __shared__ T taub[2][CPW];
-  const int t = threadIdx.x;
-  const int c = t / TPC, rg = t % TPC;
-  const int wave = t / kWave;
+template <int NC, class T>
+__global__ __launch_bounds__(kQrWaves * kWave) void qr_block_kernel(const T* __restrict__ in, int64_t ldin, int64_t p_total,
+                                                                    int64_t rows_per_block, int n, T* __restrict__ out) {
+  constexpr int ER = kQrMaxRows / kWave;  // rows per lane
+  __shared__ T vbuf[2][kQrMaxRows];
+  __shared__ T taub[2];
+  const int wave = threadIdx.x / kWave, lane = lane_id();
   const int64_t r_beg = (int64_t)blockIdx.x * rows_per_block;
   const int64_t p64 = p_total - r_beg < rows_per_block ? p_total - r_beg : rows_per_block;
   const int p = (int)p64;
   const T* A0 = in + r_beg * ldin;
-  T a[EPT];
+  T a[NC][ER];
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int r = rg + TPC * e;
-    a[e] = (r < p && c < n) ? A0[(int64_t)r * ldin + c] : T(0);
+  for (int q = 0; q < NC; ++q) {
+    const int c = wave + kQrWaves * q;
+#pragma unroll
+    for (int e = 0; e < ER; ++e) {
+      const int r = lane + kWave * e;
+      a[q][e] = (r < p && c < n) ? A0[(int64_t)r * ldin + c] : T(0);
+    }
   }
   const int steps = n < p ? n : p;
-  // apply reflector (vb, tau) with leading row j to this thread's column
-  auto apply = [&](const T* vb, T tau, int j) {
-    T d = T(0);
+  for (int j = 0; j < steps; ++j) {
+    const int buf = j & 1;
+    if (wave == (j % kQrWaves)) {
+      const int oq = j / kQrWaves;
+      T x[ER];
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int r = rg + TPC * e;
-      if (r >= j && r < p) d = fma_t(vb[r], a[e], d);
-    }
-    d = group_sum<TPC>(d);
-    const T tw = tau * d;
+      for (int e = 0; e < ER; ++e) x[e] = T(0);
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int r = rg + TPC * e;
-      if (r >= j && r < p) a[e] = fma_t(-tw, vb[r], a[e]);
-    }
-  };
-  for (int q = 0, pi = 0; q < steps; q += CPW, ++pi) {
-    const int buf = pi & 1;
-    const int qend = q + CPW < steps ? q + CPW : steps;
-    if (wave == q / CPW) {
-      for (int j = q; j < qend; ++j) {
-        const int jj = j - q;
-        if (c == j) {
-          T ss = T(0), alpha = T(0);
+      for (int q = 0; q < NC; ++q)
+        if (q == oq) {
 #pragma unroll
-          for (int e = 0; e < EPT; ++e) {
-            const int r = rg + TPC * e;
-            if (r > j) ss = fma_t(a[e], a[e], ss);
-            if (r == j) alpha = a[e];
-          }
-          ss = group_sum<TPC>(ss);
-          alpha = group_sum<TPC>(alpha);  // only the owner of row j holds a nonzero term
-          T tau = T(0), beta = alpha, scal = T(0);
-          if (ss != T(0)) {
-            beta = -copysign(sqrt(fma_t(alpha, alpha, ss)), alpha);
-            tau = (beta - alpha) / beta;
-            scal = T(1) / (alpha - beta);
-          }
-#pragma unroll
-          for (int e = 0; e < EPT; ++e) {
-            const int r = rg + TPC * e;
-            if (r == j) {
-              vbuf[buf][jj][r] = T(1);
-              a[e] = beta;
-            } else if (r > j) {
-              vbuf[buf][jj][r] = a[e] * scal;
-              a[e] = T(0);
-            }
-          }
-          if (rg == 0) taub[buf][jj] = tau;
+          for (int e = 0; e < ER; ++e) x[e] = a[q][e];
         }
-        wave_lds_sync();
-        if (c > j && c < qend) apply(vbuf[buf][jj], taub[buf][jj], j);
+      T ss = T(0);
+#pragma unroll
+      for (int e = 0; e < ER; ++e) {
+        const int r = lane + kWave * e;
+        if (r > j) ss = fma_t(x[e], x[e], ss);
       }
+      ss = wave_reduce_sum(ss);
+      T xsel = T(0);
+#pragma unroll
+      for (int e = 0; e < ER; ++e) xsel = (e == (j / kWave)) ? x[e] : xsel;
+      const T alpha = readlane_d(xsel, j % kWave);
+      T tau = T(0), beta = alpha, scal = T(0);
+      if (ss != T(0)) {
+        beta = -copysign(sqrt(fma_t(alpha, alpha, ss)), alpha);
+        tau = (beta - alpha) / beta;
+        scal = T(1) / (alpha - beta);
+      }
+#pragma unroll
+      for (int e = 0; e < ER; ++e) {
+        const int r = lane + kWave * e;
+        vbuf[buf][r] = (r == j) ? T(1) : (r > j ? x[e] * scal : T(0));
+        x[e] = (r == j) ? beta : (r > j ? T(0) : x[e]);
+      }
+#pragma unroll
+      for (int q = 0; q < NC; ++q)
+        if (q == oq) {
+#pragma unroll
+          for (int e = 0; e < ER; ++e) a[q][e] = x[e];
+        }
+      if (lane == 0) taub[buf] = tau;
     }
     __syncthreads();
-    if (c >= qend && c < n) {
-      for (int j = q; j < qend; ++j) apply(vbuf[buf][j - q], taub[buf][j - q], j);
+    const T tau = taub[buf];
+    if (tau != T(0)) {
+      T v[ER];
+#pragma unroll
+      for (int e = 0; e < ER; ++e) v[e] = vbuf[buf][lane + kWave * e];
+      T d[NC];
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        d[q] = T(0);
+        const int c = wave + kQrWaves * q;
+        if (c > j && c < n) {
+#pragma unroll
+          for (int e = 0; e < ER; ++e) d[q] = fma_t(v[e], a[q][e], d[q]);
+          d[q] = wave_reduce_sum(d[q]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const int c = wave + kQrWaves * q;
+        if (c > j && c < n) {
+          const T tw = tau * d[q];
+#pragma unroll
+          for (int e = 0; e < ER; ++e) a[q][e] = fma_t(-tw, v[e], a[q][e]);
+        }
+      }
     }
   }
   T* R = out + (int64_t)blockIdx.x * n * n;
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int r = rg + TPC * e;
-    if (r < n && c < n) R[r * n + c] = (c >= r) ? a[e] : T(0);
+  for (int q = 0; q < NC; ++q) {
+    const int c = wave + kQrWaves * q;
+#pragma unroll
+    for (int e = 0; e < ER; ++e) {
+      const int r = lane + kWave * e;
+      if (r < n && c < n) R[r * n + c] = (c >= r) ? a[q][e] : T(0);
+    }
   }
 }
 
@@ -130,17 +139,15 @@ template <class T>
 static hipError_t qr_blocks_any(const T* in, int64_t ldin, int64_t p_total, int64_t rows_per_block, int n, T* out, int nblocks,
                                 hipStream_t s) {
   if (rows_per_block > kQrMaxRows || n > RCQR_MAX_N || n < 1) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)nblocks);
-  if (n <= 8)
-    hipLaunchKernelGGL((qr_block_kernel<8, 64, T>), grid, dim3(8 * 64), 0, s, in, ldin, p_total, rows_per_block, n, out);
-  else if (n <= 16)
-    hipLaunchKernelGGL((qr_block_kernel<16, 16, T>), grid, dim3(16 * 16), 0, s, in, ldin, p_total, rows_per_block, n, out);
+  const dim3 grid((unsigned)nblocks), block(kQrWaves * kWave);
+  if (n <= 16)
+    hipLaunchKernelGGL((qr_block_kernel<1, T>), grid, block, 0, s, in, ldin, p_total, rows_per_block, n, out);
   else if (n <= 32)
-    hipLaunchKernelGGL((qr_block_kernel<32, 32, T>), grid, dim3(32 * 32), 0, s, in, ldin, p_total, rows_per_block, n, out);
+    hipLaunchKernelGGL((qr_block_kernel<2, T>), grid, block, 0, s, in, ldin, p_total, rows_per_block, n, out);
   else if (n <= 64)
-    hipLaunchKernelGGL((qr_block_kernel<64, 16, T>), grid, dim3(64 * 16), 0, s, in, ldin, p_total, rows_per_block, n, out);
+    hipLaunchKernelGGL((qr_block_kernel<4, T>), grid, block, 0, s, in, ldin, p_total, rows_per_block, n, out);
   else
-    hipLaunchKernelGGL((qr_block_kernel<128, 8, T>), grid, dim3(128 * 8), 0, s, in, ldin, p_total, rows_per_block, n, out);
+    hipLaunchKernelGGL((qr_block_kernel<8, T>), grid, block, 0, s, in, ldin, p_total, rows_per_block, n, out);
   return hipGetLastError();
 }
 
@@ -250,16 +257,26 @@ static __device__ double diag_sum(const double* a, int n, int ld) {
   return tr;
 }
 
-__global__ __launch_bounds__(256) void cholesky_kernel(const double* __restrict__ gc, int n, int np, const double* __restrict__ rprev,
-                                                       double shift_coef, int32_t* __restrict__ info, double* __restrict__ g_out,
-                                                       double* __restrict__ r1, double* __restrict__ r1pk, double* __restrict__ r_out,
-                                                       int64_t ldr) {
+// Cholesky for 65..128 columns: four waves; thread t holds rows 64h .. 64h+63 (h = t / 128) of
+// column c = t % 128 of G in registers.  Per step j the pivot and row j of R1 are exchanged
+// through LDS (three barriers per step).  G and R1 sit in dynamic LDS (n x n) for loading and
+// for R = R1 Rprev.
+constexpr int kChol128Threads = 256;
+
+__global__ __launch_bounds__(kChol128Threads) void cholesky_kernel(const double* __restrict__ gc, int n, int np,
+                                                                   const double* __restrict__ rprev, double shift_coef,
+                                                                   int32_t* __restrict__ info, double* __restrict__ g_out,
+                                                                   double* __restrict__ r1, double* __restrict__ r1pk,
+                                                                   double* __restrict__ r_out, int64_t ldr) {
+  constexpr int NPX = 128, HR = 64;
   extern __shared__ double g[];  // n x n
-  __shared__ int fail;
+  __shared__ double rowb[NPX];
+  __shared__ double pivb;
   __shared__ double shift;
   if (info[0] != 0) return;
+  const int t = threadIdx.x;
   const int nb = np / 16;
-  for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
+  for (int i = t; i < n * n; i += blockDim.x) {
     const int r = i / n, c = i % n;
     double v = 0.0;
     if (c >= r) {
@@ -269,64 +286,110 @@ __global__ __launch_bounds__(256) void cholesky_kernel(const double* __restrict_
     g[i] = v;
     g_out[i] = v;
   }
-  if (threadIdx.x == 0) fail = 0;
   __syncthreads();
   if (shift_coef != 0.0) {
-    if (threadIdx.x == 0) shift = shift_coef * diag_sum(g, n, n);
+    if (t == 0) shift = shift_coef * diag_sum(g, n, n);
     __syncthreads();
-    if (threadIdx.x < n) g[threadIdx.x * n + threadIdx.x] += shift;
+    if (t < n) g[t * n + t] += shift;
     __syncthreads();
   }
+  const int c = t % NPX, h = t / NPX, r0 = HR * h;
+  double col[HR];  // G[r0 + i][c]
+#pragma unroll
+  for (int i = 0; i < HR; ++i) {
+    const int r = r0 + i;
+    col[i] = (r < n && c < n && r <= c) ? g[(r < n ? r : 0) * n + (c < n ? c : 0)] : 0.0;
+  }
+  constexpr int CK = 8;
+  int bad = 0;
   for (int j = 0; j < n; ++j) {
-    const double d = g[j * n + j];
-    if (!(d > 0.0)) {  // NaN fails too
-      if (threadIdx.x == 0) {
-        info[0] = RCQR_E_CHOL;
-        info[1] = j + 1;
-        fail = 1;
+    const bool mine = (j / HR) == h;  // this thread's half holds row j
+    const int jl = j - r0;            // row j's index in this half (valid when mine)
+    double gjc = 0.0;
+    if (mine) {
+#pragma unroll
+      for (int i0 = 0; i0 < HR; i0 += CK) {
+        if (jl >= i0 && jl < i0 + CK) {
+#pragma unroll
+          for (int i = i0; i < i0 + CK; ++i) gjc = (i == jl) ? col[i] : gjc;
+        }
       }
-      break;  // uniform: every thread read the same d
-    }
-    const double rjj = sqrt(d);
-    __syncthreads();
-    for (int c = j + 1 + threadIdx.x; c < n; c += blockDim.x) g[j * n + c] = g[j * n + c] / rjj;
-    if (threadIdx.x == 0) g[j * n + j] = rjj;
-    __syncthreads();
-    const int rem = n - j - 1;
-    for (int idx = threadIdx.x; idx < rem * rem; idx += blockDim.x) {
-      const int a = j + 1 + idx / rem, b = j + 1 + idx % rem;
-      if (b >= a) g[a * n + b] = __builtin_fma(-g[j * n + a], g[j * n + b], g[a * n + b]);
+      if (c == j) pivb = gjc;
     }
     __syncthreads();
+    const double d = pivb;
+    if (!(d > 0.0)) {  // NaN fails too; every thread read the same pivot
+      bad = j + 1;
+      break;
+    }
+    if (mine) {
+      const double rjj = sqrt(d);
+      const double inv = 1.0 / rjj;
+      const double rjc = (c == j) ? rjj : (c > j ? gjc * inv : 0.0);
+#pragma unroll
+      for (int i0 = 0; i0 < HR; i0 += CK) {
+        if (jl >= i0 && jl < i0 + CK) {
+#pragma unroll
+          for (int i = i0; i < i0 + CK; ++i) col[i] = (i == jl) ? rjc : col[i];
+        }
+      }
+      rowb[c] = rjc;
+    }
+    __syncthreads();
+    const double rjc = rowb[c];
+#pragma unroll
+    for (int i0 = 0; i0 < HR; i0 += CK) {
+      if (r0 + i0 + CK - 1 > j) {
+#pragma unroll
+        for (int i = i0; i < i0 + CK; ++i) {
+          const int r = r0 + i;
+          const double rji = rowb[r];
+          const double upd = __builtin_fma(-rji, rjc, col[i]);
+          col[i] = (r > j && c >= r) ? upd : col[i];
+        }
+      }
+    }
+    __syncthreads();  // rowb and pivb are rewritten by the next step
+  }
+  if (bad) {
+    if (t == 0) {
+      info[0] = RCQR_E_CHOL;
+      info[1] = bad;
+    }
+    return;  // uniform: every thread saw the same pivot
+  }
+  if (c < n) {
+#pragma unroll
+    for (int i = 0; i < HR; ++i) {
+      const int r = r0 + i;
+      if (r < n) g[r * n + c] = (r <= c) ? col[i] : 0.0;
+    }
   }
   __syncthreads();
-  if (fail) return;
   // R1 and its packed padded form
-  for (int i = threadIdx.x; i < np * np; i += blockDim.x) {
-    const int r = i / np, c = i % np;
+  for (int i = t; i < np * np; i += blockDim.x) {
+    const int r = i / np, cc = i % np;
     double v = 0.0;
-    if (r < n && c < n) {
-      v = c >= r ? g[r * n + c] : 0.0;
-      r1[r * n + c] = v;
+    if (r < n && cc < n) {
+      v = cc >= r ? g[r * n + cc] : 0.0;
+      r1[r * n + cc] = v;
     }
-    if (c >= r) put_packed(r1pk, np, n, r, c, v);
+    if (cc >= r) put_packed(r1pk, np, n, r, cc, v);
   }
   // R = R1 Rprev (both upper triangular): R[i][k] = sum_{l=i..k} R1[i][l] Rprev[l][k]
-  for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
-    const int r = i / n, c = i % n;
+  for (int i = t; i < n * n; i += blockDim.x) {
+    const int r = i / n, cc = i % n;
     double acc = 0.0;
-    if (c >= r) {
-      for (int l = r; l <= c; ++l) acc = __builtin_fma(g[r * n + l], rprev[l * n + c], acc);
+    if (cc >= r) {
+      for (int l = r; l <= cc; ++l) acc = __builtin_fma(g[r * n + l], rprev[l * n + cc], acc);
     }
-    r_out[(int64_t)r * ldr + c] = acc;
+    r_out[(int64_t)r * ldr + cc] = acc;
   }
 }
 
-// Cholesky for np <= 64 with short, rolled loops (a fully unrolled single-wave factorization
-// is tens of KB of straight-line code that runs once and is bound by instruction fetch).
-// G lives in LDS (row-major, upper triangle; the lower triangle is scratch).  Wave 0 factors:
-// step j divides row j by sqrt(G[j][j]) and lane c updates column c below row j,
-// G[i][c] -= R1[j][i] R1[j][c] for j < i <= c.  Then all four waves form R = R1 Rprev.
+// Cholesky for np <= 64.  Wave 0 factors with column c of G in lane c's registers (the step
+// loop is rolled, the loop over rows unrolled, so the code stays small); R1 goes back to LDS and
+// all four waves form R = R1 Rprev.
 template <int NP>
 __global__ __launch_bounds__(256) void cholesky_small_kernel(const double* __restrict__ gc, int n, const double* __restrict__ rprev,
                                                              double shift_coef, int32_t* __restrict__ info, double* __restrict__ g_out,
@@ -334,6 +397,7 @@ __global__ __launch_bounds__(256) void cholesky_small_kernel(const double* __res
                                                              int64_t ldr) {
   __shared__ double G[NP * NP];
   __shared__ double P[NP * NP];  // Rprev, zero-padded
+  __shared__ double rowb[NP];
   __shared__ int fail;
   __shared__ double shift;
   if (info[0] != 0) return;
@@ -359,23 +423,59 @@ __global__ __launch_bounds__(256) void cholesky_small_kernel(const double* __res
     __syncthreads();
   }
   if (t < kWave) {
+    // lane c holds column c of G in registers; step j: row j of R1 is R1[j][c] = G[j][c] / r_jj,
+    // then G[i][c] -= R1[j][i] R1[j][c] for j < i <= c with R1[j][i] broadcast through LDS.
+    // Rows go in chunks of 8: a chunk wholly at or above row j is skipped (uniform branch), the
+    // rest is branch-free so the LDS reads pipeline.
+    constexpr int CK = 8;
     const int c = t;
+    double g[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) g[i] = (c < NP) ? G[i * NP + (c < NP ? c : 0)] : 0.0;
+    int bad = 0;
     for (int j = 0; j < n; ++j) {
-      const double d = G[j * NP + j];
+      double gjc = 0.0;
+#pragma unroll
+      for (int i0 = 0; i0 < NP; i0 += CK) {
+        if (j >= i0 && j < i0 + CK) {
+#pragma unroll
+          for (int i = i0; i < i0 + CK; ++i) gjc = (i == j) ? g[i] : gjc;
+        }
+      }
+      const double d = readlane_d(gjc, j);
       if (!(d > 0.0)) {  // NaN fails too; uniform across the wave
-        if (c == 0) fail = j + 1;
+        bad = j + 1;
         break;
       }
       const double rjj = sqrt(d);
       const double inv = 1.0 / rjj;
-      if (c > j && c < n) G[j * NP + c] *= inv;
-      if (c == j) G[j * NP + j] = rjj;
+      const double rjc = (c == j) ? rjj : (c > j ? gjc * inv : 0.0);
+#pragma unroll
+      for (int i0 = 0; i0 < NP; i0 += CK) {
+        if (j >= i0 && j < i0 + CK) {
+#pragma unroll
+          for (int i = i0; i < i0 + CK; ++i) g[i] = (i == j) ? rjc : g[i];
+        }
+      }
+      if (c < NP) rowb[c] = rjc;
       wave_lds_sync();
-      if (c > j && c < n) {
-        const double rjc = G[j * NP + c];
-        for (int i = j + 1; i <= c; ++i) G[i * NP + c] = __builtin_fma(-G[j * NP + i], rjc, G[i * NP + c]);
+#pragma unroll
+      for (int i0 = 0; i0 < NP; i0 += CK) {
+        if (i0 + CK - 1 > j) {
+#pragma unroll
+          for (int i = i0; i < i0 + CK; ++i) {
+            const double rji = rowb[i];
+            const double upd = __builtin_fma(-rji, rjc, g[i]);
+            g[i] = (i > j && c >= i) ? upd : g[i];
+          }
+        }
       }
       wave_lds_sync();
+    }
+    if (c == 0) fail = bad;
+    if (c < NP) {
+#pragma unroll
+      for (int i = 0; i < NP; ++i) G[i * NP + c] = (i <= c) ? g[i] : 0.0;
     }
   }
   __syncthreads();
@@ -423,7 +523,8 @@ hipError_t launch_cholesky(const double* gcompact, int n, int np, const double* 
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(256), lds, s, gcompact, n, np, rprev, shift_coef, info, g_out, r1, r1pk, r_out, ldr);
+  hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(kChol128Threads), lds, s, gcompact, n, np, rprev, shift_coef, info, g_out, r1,
+                     r1pk, r_out, ldr);
   return hipGetLastError();
 }
 

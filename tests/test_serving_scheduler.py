@@ -1,0 +1,87 @@
+"""Host logic of the continuous-batching loop (no GPU): a simulated backend with known service
+times checks admission order, the slot and memory limits, and the latency bookkeeping."""
+
+import pytest
+
+from paper_2309_05868_amd.serve import Scheduler, latency_summary
+
+
+class FakeBackend:
+    """Simulated clock: it advances by one tick on every poll and every read of the time, so the
+    loop never waits on the wall clock."""
+
+    def __init__(self, tick=1e-4):
+        self.t = 0.0
+        self.tick = tick
+        self.launched = []
+        self.inflight_bytes = 0
+        self.max_bytes = 0
+
+    def now(self):
+        self.t += self.tick
+        return self.t
+
+    def footprint(self, req):
+        return req["bytes"]
+
+    def launch(self, req, slot):
+        self.launched.append((req["id"], slot, self.t))
+        self.inflight_bytes += req["bytes"]
+        self.max_bytes = max(self.max_bytes, self.inflight_bytes)
+        return {"req": req, "end": self.t + req["work"]}
+
+    def poll(self, h):
+        self.t += self.tick
+        if self.t >= h["end"]:
+            if not h.get("done"):
+                h["done"] = True
+                self.inflight_bytes -= h["req"]["bytes"]
+            return h["end"], 0
+        return None
+
+
+def reqs(spec):
+    return [{"id": i, "arrival_s": a, "work": w, "bytes": b} for i, (a, w, b) in enumerate(spec)]
+
+
+def test_fifo_admission_within_slots_and_budget():
+    spec = [(0.000, 0.010, 40), (0.001, 0.010, 40), (0.002, 0.010, 40), (0.003, 0.001, 10), (0.050, 0.002, 90)]
+    be = FakeBackend()
+    run = Scheduler(be, slots=3, budget_bytes=100).run(reqs(spec))
+    order = [i for i, _, _ in be.launched]
+    assert order == [0, 1, 2, 3, 4]          # arrival order, never overtaken
+    assert be.max_bytes <= 100               # memory budget held
+    starts = {i: t for i, _, t in be.launched}
+    assert starts[2] >= 0.010 - 1e-9         # third 40-byte request waited for memory
+    assert starts[3] >= starts[2]            # FIFO: the small one behind it waited too
+    res = run["results"]
+    assert all(r["status"] == 0 for r in res)
+    for r in res:
+        assert r["end_s"] >= r["start_s"] >= r["arrival_s"]
+        assert r["latency_s"] == pytest.approx(r["end_s"] - r["arrival_s"])
+    assert run["peak_inflight"] <= 3
+
+
+def test_slots_limit_concurrency_and_oversized_requests_are_rejected():
+    spec = [(0.0, 0.005, 1)] * 6 + [(0.0, 0.001, 1000)]
+    be = FakeBackend()
+    run = Scheduler(be, slots=2, budget_bytes=100).run(reqs(spec))
+    assert run["peak_inflight"] == 2
+    res = run["results"]
+    assert res[6]["status"].startswith("rejected")
+    s = latency_summary(run)
+    assert s["completed"] == 6 and s["ok"] == 6
+    assert s["p99_ms"] >= s["p50_ms"] > 0
+
+
+def test_more_slots_lower_latency():
+    spec = [(0.0005 * i, 0.004, 1) for i in range(40)]
+    one = latency_summary(Scheduler(FakeBackend(), slots=1, budget_bytes=10**9).run(reqs(spec)))
+    four = latency_summary(Scheduler(FakeBackend(), slots=4, budget_bytes=10**9).run(reqs(spec)))
+    assert four["p99_ms"] < one["p99_ms"]
+    assert four["qr_per_s"] > one["qr_per_s"]
+
+
+def test_invalid_configuration():
+    with pytest.raises(ValueError):
+        Scheduler(FakeBackend(), slots=0, budget_bytes=10)
