@@ -60,6 +60,27 @@ def phase_model(name, m, n):
     return None, None
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "rand_cholqr_2Mx64_hbm_traffic.txt")
+TRAFFIC_SOURCES = ["paper_2309_05868_amd/csrc/stream.hip", "paper_2309_05868_amd/csrc/device_common.h"]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of the dominant kernel from the committed FETCH_SIZE / WRITE_SIZE
+    summary, or None when there is none for this kernel or the kernel source changed since."""
+    import hashlib
+    import re
+
+    if kernel != "final" or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    text = open(TRAFFIC_PROFILE).read()
+    mb = re.search(r"traffic_bytes_per_launch (\d+)", text)
+    mh = re.search(r"sha256 \(.*?\): ([0-9a-f]{64})", text)
+    if not mb or not mh:
+        return None
+    h = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read() for f in TRAFFIC_SOURCES)).hexdigest()
+    return int(mb.group(1)) if h == mh.group(1) else None
+
+
 def gram_accurate(Q, chunk=4096):
     """Q^T Q summed accurately: exact-size chunk Grams (K = chunk) added pairwise.
 
@@ -361,12 +382,15 @@ def main():
     achieved_tf = flops / t_dom / 1e12
     if bytes_ / flops * FP64_PEAK_TFLOPS * 1e3 >= HBM_PEAK_GBS or dom != "trsm_gram":
         roofline = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": None}
+                    "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom)}
     else:
         roofline = {"bound": "alu", "achieved": round(achieved_tf, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(achieved_tf / FP64_PEAK_TFLOPS, 4), "traffic": None}
     roofline["kernel"] = dom
     roofline["kernel_ms"] = round(phases[dom], 4)
+    roofline["algorithmic_bytes"] = bytes_
+    if roofline.get("traffic") is not None:
+        roofline["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, copy-calibrated)"
 
     out = {
         "metric": METRIC, "value": round(qrs, 2), "unit": "QR/s", "n_gpus": 1, "steps": args.steps,
