@@ -250,282 +250,221 @@ __device__ __forceinline__ int upper_block_index(int a, int b, int nb) {
   return a * nb - a * (a - 1) / 2 + (b - a);
 }
 
-// trace of an LDS matrix with row stride ld, summed in index order
-static __device__ double diag_sum(const double* a, int n, int ld) {
-  double tr = 0.0;
-  for (int i = 0; i < n; ++i) tr += a[i * ld + i];
-  return tr;
-}
+// Cholesky of G (np <= 128 padded columns) by one workgroup of NWV waves, in the LDL^T order
+// and by blocks of four rows.  Thread (wave w, lane l) keeps G[i][c] in registers for the rows
+// of its row blocks, i = 4 (w + NWV kb) + r, and for columns c = l + 64 q, so no register is ever
+// indexed by a run-time value.  Step J (rows 4J .. 4J+3): the wave owning that block eliminates
+// inside it on its own (pivots and coupling coefficients read from the owning lanes; no workgroup
+// barrier), writes the four rows G[4J + r][.] and 1/pivot to LDS and, after one barrier, every
+// thread applies the rank-4 update G[i][c] -= sum_r (G[4J+r][i] / d_r) G[4J+r][c] to its rows
+// below the block (j < i <= c, branch-free).  A pivot that is not > 0 (NaN included) stops every
+// thread at the same step.  R1[j][j] = sqrt(d_j), R1[j][c] = G[j][c] / sqrt(d_j) are formed at
+// the end for all rows at once.
+template <int NP>
+struct CholShape {
+  static constexpr int NWV = NP > 64 ? 8 : 4;   // waves
+  static constexpr int CPL = NP > 64 ? 2 : 1;   // columns per lane
+  static constexpr int BR = 4;                  // rows per block
+  static constexpr int NBT = NP / (NWV * BR);   // row blocks per thread
+};
 
-// Cholesky for 65..128 columns: four waves; thread t holds rows 64h .. 64h+63 (h = t / 128) of
-// column c = t % 128 of G in registers.  Per step j the pivot and row j of R1 are exchanged
-// through LDS (three barriers per step).  G and R1 sit in dynamic LDS (n x n) for loading and
-// for R = R1 Rprev.
-constexpr int kChol128Threads = 256;
-
-__global__ __launch_bounds__(kChol128Threads) void cholesky_kernel(const double* __restrict__ gc, int n, int np,
-                                                                   const double* __restrict__ rprev, double shift_coef,
-                                                                   int32_t* __restrict__ info, double* __restrict__ g_out,
-                                                                   double* __restrict__ r1, double* __restrict__ r1pk,
-                                                                   double* __restrict__ r_out, int64_t ldr) {
-  constexpr int NPX = 128, HR = 64;
-  extern __shared__ double g[];  // n x n
-  __shared__ double rowb[NPX];
-  __shared__ double pivb;
-  __shared__ double shift;
+template <int NP>
+__global__ __launch_bounds__(CholShape<NP>::NWV * kWave) void cholesky_kernel(const double* __restrict__ gc, int n,
+                                                                              const double* __restrict__ rprev, double shift_coef,
+                                                                              int32_t* __restrict__ info, double* __restrict__ g_out,
+                                                                              double* __restrict__ r1, double* __restrict__ r1pk,
+                                                                              double* __restrict__ r_out, int64_t ldr) {
+  constexpr int NWV = CholShape<NP>::NWV, CPL = CholShape<NP>::CPL, BR = CholShape<NP>::BR, NBT = CholShape<NP>::NBT;
+  constexpr int NB = NP / 16;
+  extern __shared__ double Rl[];  // NP x NP, the rows of the LDL^T elimination
+  __shared__ double sdiag[NP];
+  __shared__ double dinvb[2][BR];
+  __shared__ int failb[2];
+  __shared__ double wsum[NWV];
   if (info[0] != 0) return;
-  const int t = threadIdx.x;
-  const int nb = np / 16;
-  for (int i = t; i < n * n; i += blockDim.x) {
-    const int r = i / n, c = i % n;
-    double v = 0.0;
-    if (c >= r) {
-      const int a = r / 16, b = c / 16;
-      v = gc[upper_block_index(a, b, nb) * 256 + (r % 16) * 16 + (c % 16)];
+  const int t = threadIdx.x, w = t / kWave, l = lane_id();
+  double g[NBT][BR][CPL];
+  double diag = 0.0;
+#pragma unroll
+  for (int kb = 0; kb < NBT; ++kb)
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+      const int i = BR * (w + NWV * kb) + r;
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) {
+        const int c = l + kWave * q;
+        double v = 0.0;
+        if (i <= c && c < n) v = gc[upper_block_index(i / 16, c / 16, NB) * 256 + (i % 16) * 16 + (c % 16)];
+        g[kb][r][q] = v;
+        if (i == c) diag += v;
+        if (i < n && c < n) g_out[i * n + c] = v;
+      }
     }
-    g[i] = v;
-    g_out[i] = v;
-  }
-  __syncthreads();
-  if (shift_coef != 0.0) {
-    if (t == 0) shift = shift_coef * diag_sum(g, n, n);
+  if (shift_coef != 0.0) {  // G + shift_coef * trace(G) * I; the trace summed in a fixed order
+    const double ws = wave_reduce_sum(diag);
+    if (l == 0) wsum[w] = ws;
     __syncthreads();
-    if (t < n) g[t * n + t] += shift;
-    __syncthreads();
-  }
-  const int c = t % NPX, h = t / NPX, r0 = HR * h;
-  double col[HR];  // G[r0 + i][c]
+    double tr = 0.0;
+    for (int k = 0; k < NWV; ++k) tr += wsum[k];
+    const double shift = shift_coef * tr;
 #pragma unroll
-  for (int i = 0; i < HR; ++i) {
-    const int r = r0 + i;
-    col[i] = (r < n && c < n && r <= c) ? g[(r < n ? r : 0) * n + (c < n ? c : 0)] : 0.0;
+    for (int kb = 0; kb < NBT; ++kb)
+#pragma unroll
+      for (int r = 0; r < BR; ++r)
+#pragma unroll
+        for (int q = 0; q < CPL; ++q)
+          if (BR * (w + NWV * kb) + r == l + kWave * q && l + kWave * q < n) g[kb][r][q] += shift;
   }
-  constexpr int CK = 8;
   int bad = 0;
-  for (int j = 0; j < n; ++j) {
-    const bool mine = (j / HR) == h;  // this thread's half holds row j
-    const int jl = j - r0;            // row j's index in this half (valid when mine)
-    double gjc = 0.0;
-    if (mine) {
+  const int nblk = (n + BR - 1) / BR;
+  for (int J = 0; J < nblk; ++J) {
+    const int buf = J & 1;
+    const int j0 = BR * J;
+    if (w == J % NWV) {
+      const int kJ = J / NWV;
+      double rows[BR][CPL];
 #pragma unroll
-      for (int i0 = 0; i0 < HR; i0 += CK) {
-        if (jl >= i0 && jl < i0 + CK) {
+      for (int r = 0; r < BR; ++r)
 #pragma unroll
-          for (int i = i0; i < i0 + CK; ++i) gjc = (i == jl) ? col[i] : gjc;
+        for (int q = 0; q < CPL; ++q) {
+          double v = 0.0;
+#pragma unroll
+          for (int kb = 0; kb < NBT; ++kb) v = (kb == kJ) ? g[kb][r][q] : v;
+          rows[r][q] = v;
+        }
+      // column j0 + r lives in lane (j0 + r) % 64 of part (j0 + r) / 64 (the same part for the block)
+      const int qj = (CPL > 1 && j0 >= kWave) ? 1 : 0;
+      int fail = 0;
+#pragma unroll
+      for (int r = 0; r < BR; ++r) {
+        const int j = j0 + r;
+        const double d = readlane_d(qj ? rows[r][CPL - 1] : rows[r][0], j % kWave);
+        const bool live = j < n;
+        if (live && !(d > 0.0) && fail == 0) fail = j + 1;
+        const double dinv = 1.0 / d;
+        if (l == 0) dinvb[buf][r] = live ? dinv : 0.0;
+#pragma unroll
+        for (int r2 = r + 1; r2 < BR; ++r2) {
+          const double coef = readlane_d(qj ? rows[r][CPL - 1] : rows[r][0], (j0 + r2) % kWave) * dinv;
+#pragma unroll
+          for (int q = 0; q < CPL; ++q) {
+            const int c = l + kWave * q;
+            const double upd = __builtin_fma(-coef, rows[r][q], rows[r2][q]);
+            rows[r2][q] = (live && c >= j0 + r2) ? upd : rows[r2][q];
+          }
         }
       }
-      if (c == j) pivb = gjc;
+#pragma unroll
+      for (int r = 0; r < BR; ++r)
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+          const int c = l + kWave * q;
+          if (c < NP && j0 + r < NP) Rl[(j0 + r) * NP + c] = (c >= j0 + r) ? rows[r][q] : 0.0;
+        }
+      if (l == 0) failb[buf] = fail;
     }
     __syncthreads();
-    const double d = pivb;
-    if (!(d > 0.0)) {  // NaN fails too; every thread read the same pivot
-      bad = j + 1;
+    const int f = failb[buf];
+    if (f) {  // every thread read the same flag
+      bad = f;
       break;
     }
-    if (mine) {
-      const double rjj = sqrt(d);
-      const double inv = 1.0 / rjj;
-      const double rjc = (c == j) ? rjj : (c > j ? gjc * inv : 0.0);
+    double gj[BR][CPL], di[BR];
 #pragma unroll
-      for (int i0 = 0; i0 < HR; i0 += CK) {
-        if (jl >= i0 && jl < i0 + CK) {
+    for (int r = 0; r < BR; ++r) {
+      di[r] = dinvb[buf][r];
 #pragma unroll
-          for (int i = i0; i < i0 + CK; ++i) col[i] = (i == jl) ? rjc : col[i];
-        }
-      }
-      rowb[c] = rjc;
-    }
-    __syncthreads();
-    const double rjc = rowb[c];
-#pragma unroll
-    for (int i0 = 0; i0 < HR; i0 += CK) {
-      if (r0 + i0 + CK - 1 > j) {
-#pragma unroll
-        for (int i = i0; i < i0 + CK; ++i) {
-          const int r = r0 + i;
-          const double rji = rowb[r];
-          const double upd = __builtin_fma(-rji, rjc, col[i]);
-          col[i] = (r > j && c >= r) ? upd : col[i];
-        }
+      for (int q = 0; q < CPL; ++q) {
+        const int c = l + kWave * q;
+        gj[r][q] = (c < NP) ? Rl[(j0 + r) * NP + (c < NP ? c : 0)] : 0.0;
       }
     }
-    __syncthreads();  // rowb and pivb are rewritten by the next step
+#pragma unroll
+    for (int kb = 0; kb < NBT; ++kb)
+#pragma unroll
+      for (int r2 = 0; r2 < BR; ++r2) {
+        const int i = BR * (w + NWV * kb) + r2;
+        double lij[BR];
+#pragma unroll
+        for (int r = 0; r < BR; ++r) lij[r] = Rl[(j0 + r) * NP + i] * di[r];
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+          const int c = l + kWave * q;
+          double upd = g[kb][r2][q];
+#pragma unroll
+          for (int r = 0; r < BR; ++r) upd = __builtin_fma(-lij[r], gj[r][q], upd);
+          g[kb][r2][q] = (i >= j0 + BR && i <= c) ? upd : g[kb][r2][q];
+        }
+      }
   }
   if (bad) {
     if (t == 0) {
       info[0] = RCQR_E_CHOL;
       info[1] = bad;
     }
-    return;  // uniform: every thread saw the same pivot
-  }
-  if (c < n) {
-#pragma unroll
-    for (int i = 0; i < HR; ++i) {
-      const int r = r0 + i;
-      if (r < n) g[r * n + c] = (r <= c) ? col[i] : 0.0;
-    }
+    return;
   }
   __syncthreads();
-  // R1 and its packed padded form
-  for (int i = t; i < np * np; i += blockDim.x) {
-    const int r = i / np, cc = i % np;
-    double v = 0.0;
-    if (r < n && cc < n) {
-      v = cc >= r ? g[r * n + cc] : 0.0;
-      r1[r * n + cc] = v;
-    }
-    if (cc >= r) put_packed(r1pk, np, n, r, cc, v);
+  // rows of R1 from the stored rows of the LDL^T factorization
+  for (int r = t; r < n; r += blockDim.x) sdiag[r] = sqrt(Rl[r * NP + r]);
+  __syncthreads();
+  for (int idx = t; idx < n * NP; idx += blockDim.x) {
+    const int r = idx / NP, c = idx % NP;
+    const double sr = sdiag[r];
+    Rl[idx] = (c == r) ? sr : ((c > r && c < n) ? Rl[idx] / sr : 0.0);
   }
-  // R = R1 Rprev (both upper triangular): R[i][k] = sum_{l=i..k} R1[i][l] Rprev[l][k]
-  for (int i = t; i < n * n; i += blockDim.x) {
-    const int r = i / n, cc = i % n;
+  __syncthreads();
+  // R1, its packed padded form, and R = R1 Rprev: R[i][k] = sum_{m = i..k} R1[i][m] Rprev[m][k]
+  for (int idx = t; idx < NP * NP; idx += blockDim.x) {
+    const int r = idx / NP, c = idx % NP;
+    const double v = (r < n && c < n && c >= r) ? Rl[r * NP + c] : 0.0;
+    if (r < n && c < n) r1[r * n + c] = v;
+    if (c >= r) put_packed(r1pk, NP, n, r, c, v);
+  }
+  for (int idx = t; idx < n * n; idx += blockDim.x) {
+    const int r = idx / n, k = idx % n;
     double acc = 0.0;
-    if (cc >= r) {
-      for (int l = r; l <= cc; ++l) acc = __builtin_fma(g[r * n + l], rprev[l * n + cc], acc);
+    if (k >= r) {
+      int m = r;
+      for (; m + 8 <= k + 1; m += 8) {  // eight independent loads in flight
+        double pv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) pv[u] = rprev[(m + u) * n + k];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = __builtin_fma(Rl[r * NP + m + u], pv[u], acc);
+      }
+      for (; m <= k; ++m) acc = __builtin_fma(Rl[r * NP + m], rprev[m * n + k], acc);
     }
-    r_out[(int64_t)r * ldr + cc] = acc;
+    r_out[(int64_t)r * ldr + k] = acc;
   }
 }
 
-// Cholesky for np <= 64.  Wave 0 factors with column c of G in lane c's registers (the step
-// loop is rolled, the loop over rows unrolled, so the code stays small); R1 goes back to LDS and
-// all four waves form R = R1 Rprev.
 template <int NP>
-__global__ __launch_bounds__(256) void cholesky_small_kernel(const double* __restrict__ gc, int n, const double* __restrict__ rprev,
-                                                             double shift_coef, int32_t* __restrict__ info, double* __restrict__ g_out,
-                                                             double* __restrict__ r1, double* __restrict__ r1pk, double* __restrict__ r_out,
-                                                             int64_t ldr) {
-  __shared__ double G[NP * NP];
-  __shared__ double P[NP * NP];  // Rprev, zero-padded
-  __shared__ double rowb[NP];
-  __shared__ int fail;
-  __shared__ double shift;
-  if (info[0] != 0) return;
-  constexpr int NB = NP / 16;
-  const int t = threadIdx.x;
-  for (int idx = t; idx < NP * NP; idx += blockDim.x) {
-    const int i = idx / NP, c = idx % NP;
-    double v = 0.0, pv = 0.0;
-    if (i <= c && c < n) {
-      v = gc[upper_block_index(i / 16, c / 16, NB) * 256 + (i % 16) * 16 + (c % 16)];
-      pv = rprev[i * n + c];
-    }
-    G[idx] = v;
-    P[idx] = pv;
-    if (i < n && c < n) g_out[i * n + c] = v;
-  }
-  if (t == 0) fail = 0;
-  __syncthreads();
-  if (shift_coef != 0.0) {
-    if (t == 0) shift = shift_coef * diag_sum(G, n, NP);
-    __syncthreads();
-    if (t < n) G[t * NP + t] += shift;
-    __syncthreads();
-  }
-  if (t < kWave) {
-    // lane c holds column c of G in registers; step j: row j of R1 is R1[j][c] = G[j][c] / r_jj,
-    // then G[i][c] -= R1[j][i] R1[j][c] for j < i <= c with R1[j][i] broadcast through LDS.
-    // Rows go in chunks of 8: a chunk wholly at or above row j is skipped (uniform branch), the
-    // rest is branch-free so the LDS reads pipeline.
-    constexpr int CK = 8;
-    const int c = t;
-    double g[NP];
-#pragma unroll
-    for (int i = 0; i < NP; ++i) g[i] = (c < NP) ? G[i * NP + (c < NP ? c : 0)] : 0.0;
-    int bad = 0;
-    for (int j = 0; j < n; ++j) {
-      double gjc = 0.0;
-#pragma unroll
-      for (int i0 = 0; i0 < NP; i0 += CK) {
-        if (j >= i0 && j < i0 + CK) {
-#pragma unroll
-          for (int i = i0; i < i0 + CK; ++i) gjc = (i == j) ? g[i] : gjc;
-        }
-      }
-      const double d = readlane_d(gjc, j);
-      if (!(d > 0.0)) {  // NaN fails too; uniform across the wave
-        bad = j + 1;
-        break;
-      }
-      const double rjj = sqrt(d);
-      const double inv = 1.0 / rjj;
-      const double rjc = (c == j) ? rjj : (c > j ? gjc * inv : 0.0);
-#pragma unroll
-      for (int i0 = 0; i0 < NP; i0 += CK) {
-        if (j >= i0 && j < i0 + CK) {
-#pragma unroll
-          for (int i = i0; i < i0 + CK; ++i) g[i] = (i == j) ? rjc : g[i];
-        }
-      }
-      if (c < NP) rowb[c] = rjc;
-      wave_lds_sync();
-#pragma unroll
-      for (int i0 = 0; i0 < NP; i0 += CK) {
-        if (i0 + CK - 1 > j) {
-#pragma unroll
-          for (int i = i0; i < i0 + CK; ++i) {
-            const double rji = rowb[i];
-            const double upd = __builtin_fma(-rji, rjc, g[i]);
-            g[i] = (i > j && c >= i) ? upd : g[i];
-          }
-        }
-      }
-      wave_lds_sync();
-    }
-    if (c == 0) fail = bad;
-    if (c < NP) {
-#pragma unroll
-      for (int i = 0; i < NP; ++i) G[i * NP + c] = (i <= c) ? g[i] : 0.0;
+static hipError_t cholesky_any(const double* gcompact, int n, const double* rprev, double shift_coef, int32_t* info, double* g_out,
+                               double* r1, double* r1pk, double* r_out, int64_t ldr, hipStream_t s) {
+  const size_t lds = (size_t)NP * NP * sizeof(double);
+  if (lds > 64 * 1024) {
+    static bool attr_set = false;  // 128 x 128 needs 128 KiB of dynamic LDS
+    if (!attr_set) {
+      const hipError_t e = hipFuncSetAttribute((const void*)cholesky_kernel<NP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      attr_set = true;
     }
   }
-  __syncthreads();
-  if (fail) {
-    if (t == 0) {
-      info[0] = RCQR_E_CHOL;
-      info[1] = fail;
-    }
-    return;
-  }
-  // R1, its packed padded form, and R = R1 Rprev: R[i][c] = sum_{l = i..c} R1[i][l] Rprev[l][c]
-  for (int idx = t; idx < NP * NP; idx += blockDim.x) {
-    const int i = idx / NP, c = idx % NP;
-    const double v = (i <= c && c < n) ? G[idx] : 0.0;
-    if (i < n && c < n) r1[i * n + c] = v;
-    if (c >= i) put_packed(r1pk, NP, n, i, c, v);
-    if (i < n && c < n) {
-      double acc = 0.0;
-      if (i <= c)
-        for (int l = i; l <= c; ++l) acc = __builtin_fma(G[i * NP + l], P[l * NP + c], acc);
-      r_out[(int64_t)i * ldr + c] = acc;
-    }
-  }
+  hipLaunchKernelGGL(cholesky_kernel<NP>, dim3(1), dim3(CholShape<NP>::NWV * kWave), lds, s, gcompact, n, rprev, shift_coef, info,
+                     g_out, r1, r1pk, r_out, ldr);
+  return hipGetLastError();
 }
 
 hipError_t launch_cholesky(const double* gcompact, int n, int np, const double* rprev, double shift_coef, int32_t* info,
                            double* g_out, double* r1, double* r1pk, double* r_out, int64_t ldr, hipStream_t s) {
-  if (np == 16) {
-    hipLaunchKernelGGL(cholesky_small_kernel<16>, dim3(1), dim3(256), 0, s, gcompact, n, rprev, shift_coef, info, g_out, r1, r1pk, r_out, ldr);
-    return hipGetLastError();
+  switch (np) {
+    case 16: return cholesky_any<16>(gcompact, n, rprev, shift_coef, info, g_out, r1, r1pk, r_out, ldr, s);
+    case 32: return cholesky_any<32>(gcompact, n, rprev, shift_coef, info, g_out, r1, r1pk, r_out, ldr, s);
+    case 64: return cholesky_any<64>(gcompact, n, rprev, shift_coef, info, g_out, r1, r1pk, r_out, ldr, s);
+    case 128: return cholesky_any<128>(gcompact, n, rprev, shift_coef, info, g_out, r1, r1pk, r_out, ldr, s);
+    default: return hipErrorInvalidValue;
   }
-  if (np == 32) {
-    hipLaunchKernelGGL(cholesky_small_kernel<32>, dim3(1), dim3(256), 0, s, gcompact, n, rprev, shift_coef, info, g_out, r1, r1pk, r_out, ldr);
-    return hipGetLastError();
-  }
-  if (np == 64) {
-    hipLaunchKernelGGL(cholesky_small_kernel<64>, dim3(1), dim3(256), 0, s, gcompact, n, rprev, shift_coef, info, g_out, r1, r1pk, r_out, ldr);
-    return hipGetLastError();
-  }
-  const size_t lds = (size_t)n * n * sizeof(double);
-  static bool attr_set = false;  // G of 128 x 128 needs 128 KiB of dynamic LDS
-  if (!attr_set) {
-    const hipError_t e = hipFuncSetAttribute((const void*)cholesky_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             RCQR_MAX_N * RCQR_MAX_N * (int)sizeof(double));
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(kChol128Threads), lds, s, gcompact, n, np, rprev, shift_coef, info, g_out, r1,
-                     r1pk, r_out, ldr);
-  return hipGetLastError();
 }
 
 }  // namespace rcqr
