@@ -16,6 +16,7 @@ timed region), and the CPU oracle timed on a bounded sample of the same workload
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-comparators]
   python bench.py --workload mixed     # precision variants, m = 4e6, n = 128, kappa = 1e14
   python bench.py --workload serve     # 4096 requests, continuous batching vs one at a time
+  python bench.py --workload latency   # small factorizations, eager vs HIP graph
 """
 
 import argparse
@@ -265,6 +266,67 @@ def serve_workload(args):
     print(json.dumps(line), flush=True)
 
 
+LATENCY_SHAPES = [dict(m=10_000, n=16, kappa=1e4, s1=512, s2=64, seed=0),
+                  dict(m=100_000, n=64, kappa=1e8, s1=8192, s2=256, seed=0)]
+
+
+def latency_workload(args):
+    """Small factorizations, launch-bound: eager calls against a captured HIP graph of the same
+    plan, back to back (QR/s) and one at a time with a synchronisation each (p50 latency)."""
+    import numpy as np
+    import torch
+
+    import paper_2309_05868_amd as rc
+    import synth
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(dev)
+    out = []
+    for wl in LATENCY_SHAPES:
+        m, n = wl["m"], wl["n"]
+        V = torch.from_numpy(synth.make_V(m, n, wl["kappa"], wl["seed"])).to(dev)
+        with torch.cuda.stream(stream):
+            plan = rc.Plan(m, n, wl["s1"], wl["s2"], wl["seed"], device=dev, stream=stream)
+            Q = torch.empty_like(V)
+            R = torch.empty((n, n), dtype=torch.float64, device=dev)
+            graph = plan.graph(V, Q, R)
+            rec = {"workload": f"m={m} n={n} kappa={wl['kappa']:.0e} s1={wl['s1']} s2={wl['s2']}"}
+            for name, call in (("eager", lambda: plan.factor(V, Q, R, check=False)), ("graph", graph.launch)):
+                for _ in range(args.warmup + 3):
+                    call()
+                stream.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                reps = max(args.steps, 50)
+                e0.record(stream)
+                for _ in range(reps):
+                    call()
+                e1.record(stream)
+                e1.synchronize()
+                back_to_back = e0.elapsed_time(e1) / reps
+                lat = []
+                for _ in range(reps):
+                    t0 = time.perf_counter()
+                    call()
+                    stream.synchronize()
+                    lat.append(1e3 * (time.perf_counter() - t0))
+                lat.sort()
+                rec[name] = {"ms_per_qr_back_to_back": round(back_to_back, 4), "qr_per_s": round(1e3 / back_to_back, 1),
+                             "p50_ms_single": round(lat[len(lat) // 2], 4), "p99_ms_single": round(lat[int(0.99 * (len(lat) - 1))], 4)}
+            st, _ = plan.info()
+            eye = torch.eye(n, dtype=torch.float64, device=dev)
+            rec["status"] = st
+            rec["orth_error"] = torch.linalg.norm(eye - gram_accurate(Q)).item()
+            rec["within_target"] = bool(rec["orth_error"] <= 10 * n * U_PAPER)
+            graph.close()
+            plan.close()
+        out.append(rec)
+    line = {"metric": METRIC, "value": out[0]["graph"]["qr_per_s"], "unit": "QR/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic", "config": {"workload": "rand_cholQR small factorizations, eager vs HIP graph"},
+            "shapes": out}
+    print(json.dumps(line), flush=True)
+
+
 def cpu_baseline(wl, sample_rows):
     """The oracle as it stands, single-threaded, on a row-scaled sample of the workload."""
     from threadpoolctl import threadpool_limits
@@ -296,9 +358,10 @@ def main():
     ap.add_argument("--no-comparators", action="store_true", help="skip timing cholQR2 and sCholQR3 on the same V")
     ap.add_argument("--comparator-steps", type=int, default=5)
     ap.add_argument("--cpu-sample-rows", type=int, default=100_000)
-    ap.add_argument("--workload", choices=["default", "mixed", "serve"], default="default",
+    ap.add_argument("--workload", choices=["default", "mixed", "serve", "latency"], default="default",
                     help="mixed: FP32/BF16 preconditioner variants against FP64 at m=4e6, n=128, kappa=1e14; "
-                         "serve: continuous batching of 4096 Poisson-arriving requests")
+                         "serve: continuous batching of 4096 Poisson-arriving requests; "
+                         "latency: small factorizations, eager vs HIP graph")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-budget-gb", type=int, default=64)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -333,6 +396,9 @@ def main():
         return
     if args.workload == "serve":
         serve_workload(args)
+        return
+    if args.workload == "latency":
+        latency_workload(args)
         return
     wl = WORKLOAD
     m, n = wl["m"], wl["n"]

@@ -153,6 +153,28 @@ rcqr_status_t rcqr_set_timing(rcqr_plan_t plan, int32_t steps);
 rcqr_status_t rcqr_phase_times(rcqr_plan_t plan, float* ms, int32_t max, int32_t* count);
 const char* rcqr_phase_name(int32_t phase);
 
+/*
+ * HIP graphs.  rcqr_graph_create() records one factorization of the given V into Q and R
+ * (method RCQR_METHOD_RAND_CHOLQR = rcqr_factor, RCQR_METHOD_CHOLQR2, RCQR_METHOD_SCHOLQR3) by
+ * stream capture on the plan's stream and instantiates it; nothing runs during the capture.
+ * rcqr_graph_launch() replays it on the plan's stream: one launch instead of about fifteen, for
+ * callers that factor same-shaped inputs from fixed buffers (small m, where launches dominate).
+ * The plan must have been created with a stream other than the legacy default stream
+ * (RCQR_E_INVALID otherwise) and with timing off or on (events are not recorded in the graph).
+ * The plan, its workspace, V, Q and R must stay valid while the graph is used; destroy the graph
+ * before the plan.  Replays and eager calls on the same plan share its workspace: issue them on
+ * the plan's stream only (they are then ordered).  A failure is reported by rcqr_info() as for
+ * an eager call.
+ */
+typedef struct rcqr_graph_s* rcqr_graph_t;
+#define RCQR_METHOD_RAND_CHOLQR 0
+#define RCQR_METHOD_CHOLQR2 1
+#define RCQR_METHOD_SCHOLQR3 2
+rcqr_status_t rcqr_graph_create(rcqr_plan_t plan, int32_t method, const double* d_V, int64_t ldv, double* d_Q,
+                                int64_t ldq, double* d_R, int64_t ldr, rcqr_graph_t* graph);
+rcqr_status_t rcqr_graph_launch(rcqr_graph_t graph);
+rcqr_status_t rcqr_graph_destroy(rcqr_graph_t graph);
+
 /* ------------------------------------------------------------------------------------------
  * Inspection entry points (same library; used by tests, never on a timed path).
  * ------------------------------------------------------------------------------------------ */

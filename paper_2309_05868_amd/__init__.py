@@ -22,6 +22,7 @@ OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_HIP, E_RANK, E_CHOL = range(7)
 MAX_N = 128  # largest number of columns the kernels accept
 # plan flags (include/rcqr.h): single-precision sketch, BF16 Gaussian product, second Cholesky QR
 FLAG_SKETCH_FP32, FLAG_GEMM_BF16, FLAG_REORTH = 1, 2, 4
+METHODS = {"rand_cholqr": 0, "cholqr2": 1, "scholqr3": 2}
 
 _lib = None
 
@@ -43,6 +44,9 @@ _SIGNATURES = {
     "rcqr_gaussian_block": (_c_i32, [_c_p, _c_i64, _c_i64, _c_i64, _c_i64, _c_p]),
     "rcqr_intermediates": (_c_i32, [_c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "rcqr_q0_twice": (_c_i32, [_c_p, _c_p, _c_i64, _c_p, _c_p, _c_i64]),
+    "rcqr_graph_create": (_c_i32, [_c_p, _c_i32, _c_p, _c_i64, _c_p, _c_i64, _c_p, _c_i64, ctypes.POINTER(_c_p)]),
+    "rcqr_graph_launch": (_c_i32, [_c_p]),
+    "rcqr_graph_destroy": (_c_i32, [_c_p]),
 }
 
 
@@ -180,6 +184,16 @@ class Plan:
         if st != OK:
             raise RcqrError(st, what, col)
 
+    def graph(self, V, Q=None, R=None, method="rand_cholqr"):
+        """Capture one factorization of V into (Q, R) as a HIP graph; returns a Graph whose
+        launch() replays it on this plan's stream.  Needs a plan on a non-default stream."""
+        Q, R = self._outputs(V, Q, R)
+        h = ctypes.c_void_p()
+        _check(lib().rcqr_graph_create(self._h, METHODS[method], ctypes.c_void_p(V.data_ptr()), V.stride(0),
+                                       ctypes.c_void_p(Q.data_ptr()), Q.stride(0), ctypes.c_void_p(R.data_ptr()), R.stride(0),
+                                       ctypes.byref(h)), "rcqr_graph_create")
+        return Graph(self, h, V, Q, R)
+
     # -- timing ----------------------------------------------------------------------------
     def set_timing(self, steps=1):
         """Record per-phase HIP events for the next `steps` factor calls (0 turns it off)."""
@@ -220,6 +234,31 @@ class Plan:
         _check(lib().rcqr_q0_twice(self._h, ctypes.c_void_p(V.data_ptr()), V.stride(0), ctypes.c_void_p(a.data_ptr()),
                                    ctypes.c_void_p(b.data_ptr()), self.n), "rcqr_q0_twice")
         return a, b
+
+
+class Graph:
+    """A captured factorization (rcqr_graph_*): keeps the plan and the tensors it reads and
+    writes alive; launch() replays it, close() frees it (before the plan)."""
+
+    def __init__(self, plan, handle, V, Q, R):
+        self.plan, self._h, self.V, self.Q, self.R = plan, handle, V, Q, R
+
+    def launch(self, check=False):
+        _check(lib().rcqr_graph_launch(self._h), "rcqr_graph_launch")
+        if check:
+            self.plan.raise_on_failure("rcqr_graph_launch")
+        return self.Q, self.R
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rcqr_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def rand_cholqr(V, s1, s2, seed, check=True, flags=0):

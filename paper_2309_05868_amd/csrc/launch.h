@@ -70,6 +70,9 @@ hipError_t launch_finalize_r0(const float* rin, int n, int np, int32_t* info, do
 // shift_coef != 0 factors G + shift_coef * trace(G) * I instead of G.
 hipError_t launch_cholesky(const double* gcompact, int n, int np, const double* rprev, double shift_coef, int32_t* info,
                            double* g_out, double* r1, double* r1pk, double* r_out, int64_t ldr, hipStream_t s);
+// One-time host-side setup of the Cholesky kernel for np (its LDS limit); done before any
+// stream capture so that no attribute call happens inside a captured graph.
+hipError_t prepare_cholesky(int np);
 // Identity (n x n) into r0 and its packed padded form into r0pk.
 hipError_t launch_identity_factor(int n, int np, double* r0, double* r0pk, hipStream_t s);
 
@@ -82,6 +85,8 @@ int packed_len(int np);              // doubles of a packed np x np triangular f
 // row by row, the reciprocal of each diagonal entry in place of the entry.
 hipError_t launch_trsm_gram(int np, const double* V, int64_t m, int n, int64_t ldv, const double* r0pk, const int32_t* info,
                             double* gpart, double* q0, int64_t ldq, hipStream_t s);
+// Device properties the launchers read (multiprocessor count), queried once, before any capture.
+hipError_t prepare_stream_launches();
 hipError_t launch_final(int np, bool apply_r1, const double* V, int64_t m, int n, int64_t ldv, const double* r0pk,
                         const double* r1pk, const int32_t* info, double* Q, int64_t ldq, hipStream_t s);
 

@@ -521,6 +521,69 @@ rcqr_status_t rcqr_intermediates(rcqr_plan_t p, double* d_W1, double* d_W, doubl
   return RCQR_OK;
 }
 
+struct rcqr_graph_s {
+  rcqr_plan_t plan;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+rcqr_status_t rcqr_graph_create(rcqr_plan_t p, int32_t method, const double* V, int64_t ldv, double* Q, int64_t ldq, double* R,
+                                int64_t ldr, rcqr_graph_t* out) {
+  if (out == nullptr) return RCQR_E_INVALID;
+  *out = nullptr;
+  if (p == nullptr || method < RCQR_METHOD_RAND_CHOLQR || method > RCQR_METHOD_SCHOLQR3) return RCQR_E_INVALID;
+  if (p->stream == nullptr) return RCQR_E_INVALID;  // the legacy default stream cannot be captured
+  const rcqr_status_t st = check_io(p, V, ldv, Q, ldq, R, ldr);
+  if (st != RCQR_OK) return st;
+  // host-side, one-time setup outside the capture
+  RCQR_TRY(prepare_cholesky(p->sh.np));
+  RCQR_TRY(prepare_stream_launches());
+  const int cap = p->cap;
+  p->cap = 0;  // no timing events inside the graph
+  RCQR_TRY(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+  rcqr_status_t sc = RCQR_OK;
+  if (method == RCQR_METHOD_RAND_CHOLQR) sc = rcqr_factor(p, V, ldv, Q, ldq, R, ldr);
+  else if (method == RCQR_METHOD_CHOLQR2) sc = rcqr_cholqr2(p, V, ldv, Q, ldq, R, ldr);
+  else sc = rcqr_scholqr3(p, V, ldv, Q, ldq, R, ldr);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(p->stream, &graph);
+  p->cap = cap;
+  if (sc != RCQR_OK || ec != hipSuccess || graph == nullptr) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return sc != RCQR_OK ? sc : RCQR_E_HIP;
+  }
+  hipGraphExec_t exec = nullptr;
+  if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return RCQR_E_HIP;
+  }
+  rcqr_graph_s* g = new (std::nothrow) rcqr_graph_s();
+  if (g == nullptr) {
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    return RCQR_E_NOMEM;
+  }
+  g->plan = p;
+  g->graph = graph;
+  g->exec = exec;
+  *out = g;
+  return RCQR_OK;
+}
+
+rcqr_status_t rcqr_graph_launch(rcqr_graph_t g) {
+  if (g == nullptr) return RCQR_E_INVALID;
+  RCQR_TRY(hipGraphLaunch(g->exec, g->plan->stream));
+  return RCQR_OK;
+}
+
+rcqr_status_t rcqr_graph_destroy(rcqr_graph_t g) {
+  if (g == nullptr) return RCQR_E_INVALID;
+  (void)hipGraphExecDestroy(g->exec);
+  (void)hipGraphDestroy(g->graph);
+  delete g;
+  return RCQR_OK;
+}
+
 rcqr_status_t rcqr_q0_twice(rcqr_plan_t p, const double* V, int64_t ldv, double* Q0a, double* Q0b, int64_t ldq) {
   if (p == nullptr || V == nullptr || Q0a == nullptr || Q0b == nullptr || ldv < p->sh.n || ldq < p->sh.n) return RCQR_E_INVALID;
   const Shape& sh = p->sh;

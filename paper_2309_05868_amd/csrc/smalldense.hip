@@ -440,10 +440,9 @@ __global__ __launch_bounds__(CholShape<NP>::NWV * kWave) void cholesky_kernel(co
 }
 
 template <int NP>
-static hipError_t cholesky_any(const double* gcompact, int n, const double* rprev, double shift_coef, int32_t* info, double* g_out,
-                               double* r1, double* r1pk, double* r_out, int64_t ldr, hipStream_t s) {
-  const size_t lds = (size_t)NP * NP * sizeof(double);
-  if (lds > 64 * 1024) {
+static hipError_t cholesky_prepare() {
+  constexpr size_t lds = (size_t)NP * NP * sizeof(double);
+  if constexpr (lds > 64 * 1024) {
     static bool attr_set = false;  // 128 x 128 needs 128 KiB of dynamic LDS
     if (!attr_set) {
       const hipError_t e = hipFuncSetAttribute((const void*)cholesky_kernel<NP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -451,6 +450,17 @@ static hipError_t cholesky_any(const double* gcompact, int n, const double* rpre
       attr_set = true;
     }
   }
+  return hipSuccess;
+}
+
+hipError_t prepare_cholesky(int np) { return np == 128 ? cholesky_prepare<128>() : hipSuccess; }
+
+template <int NP>
+static hipError_t cholesky_any(const double* gcompact, int n, const double* rprev, double shift_coef, int32_t* info, double* g_out,
+                               double* r1, double* r1pk, double* r_out, int64_t ldr, hipStream_t s) {
+  const hipError_t e = cholesky_prepare<NP>();
+  if (e != hipSuccess) return e;
+  const size_t lds = (size_t)NP * NP * sizeof(double);
   hipLaunchKernelGGL(cholesky_kernel<NP>, dim3(1), dim3(CholShape<NP>::NWV * kWave), lds, s, gcompact, n, rprev, shift_coef, info,
                      g_out, r1, r1pk, r_out, ldr);
   return hipGetLastError();

@@ -83,6 +83,18 @@ def test_plan_rejects_bad_arguments_on_host(lib):
     finally:
         assert lib.rcqr_destroy(h) == rc.OK
     assert lib.rcqr_destroy(None) == rc.E_INVALID
+    # graphs: argument checks are host-side; a plan on the legacy default stream cannot be captured
+    g = ctypes.c_void_p()
+    assert lib.rcqr_graph_create(None, 0, p, 16, p, 16, p, 16, ctypes.byref(g)) == rc.E_INVALID
+    assert lib.rcqr_plan(ctypes.byref(h), 1000, 16, 512, 64, 0, 0, ctypes.c_void_p(1 << 20), ws, None) == rc.OK
+    try:
+        assert lib.rcqr_graph_create(h, 0, p, 16, p, 16, p, 16, ctypes.byref(g)) == rc.E_INVALID
+        assert lib.rcqr_graph_create(h, 7, p, 16, p, 16, p, 16, ctypes.byref(g)) == rc.E_INVALID
+        assert lib.rcqr_graph_create(h, 0, p, 16, p, 16, p, 16, None) == rc.E_INVALID
+    finally:
+        assert lib.rcqr_destroy(h) == rc.OK
+    assert lib.rcqr_graph_launch(None) == rc.E_INVALID
+    assert lib.rcqr_graph_destroy(None) == rc.E_INVALID
 
 
 def test_binding_refuses_cpu_tensors(lib):
