@@ -356,6 +356,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparators", action="store_true", help="skip timing cholQR2 and sCholQR3 on the same V")
+    ap.add_argument("--tune", action="store_true", help="run rcqr_tune (result-neutral launch choices) before warm-up")
     ap.add_argument("--comparator-steps", type=int, default=5)
     ap.add_argument("--cpu-sample-rows", type=int, default=100_000)
     ap.add_argument("--workload", choices=["default", "mixed", "serve", "latency"], default="default",
@@ -411,6 +412,11 @@ def main():
     plan = rc.Plan(m, n, wl["s1"], wl["s2"], wl["seed"], device=dev)
     stream = plan.stream
 
+    tuning = None
+    if args.tune:
+        mode, mult, tms = plan.tune(V, reps=3)
+        tuning = {"final_mode": ["recompute_q0", "materialize_q0"][mode], "grid_mult": mult, "tuned_ms": round(tms, 4)}
+        log(f"bench: tuned launch choice {tuning}")
     log(f"bench: warmup {args.warmup}")
     for _ in range(args.warmup):
         plan.factor(V, Q, R, check=False)
@@ -448,7 +454,8 @@ def main():
     achieved_tf = flops / t_dom / 1e12
     if bytes_ / flops * FP64_PEAK_TFLOPS * 1e3 >= HBM_PEAK_GBS or dom != "trsm_gram":
         roofline = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom)}
+                    "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic(dom) if plan.tuning()[0] == rc.FINAL_RECOMPUTE else None}
     else:
         roofline = {"bound": "alu", "achieved": round(achieved_tf, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(achieved_tf / FP64_PEAK_TFLOPS, 4), "traffic": None}
@@ -469,6 +476,7 @@ def main():
         "phase_ms": {k: round(v, 4) for k, v in phases.items()},
         "orth_error": orth, "residual": res, "target_10nu": tgt, "within_target": bool(orth <= tgt and res <= tgt),
         "roofline": roofline,
+        "tuning": tuning,
     }
     if not args.no_comparators:
         out["comparators"] = comparators(plan, V, Q, R, eye, tgt, args.comparator_steps)

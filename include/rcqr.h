@@ -154,6 +154,29 @@ rcqr_status_t rcqr_phase_times(rcqr_plan_t plan, float* ms, int32_t max, int32_t
 const char* rcqr_phase_name(int32_t phase);
 
 /*
+ * Launch tuning.  Two choices change how a factorization is launched but never its result
+ * (Q and R are bitwise the same for every setting):
+ *   final_mode  RCQR_FINAL_RECOMPUTE (default): the final pass recomputes Q0 = V R0^{-1} from V
+ *               (32 m n bytes in all); RCQR_FINAL_MATERIALIZE: the Gram pass stores Q0 in Q and
+ *               the final pass applies R1^{-1} to it in place (40 m n bytes, no second
+ *               substitution).  Only up to 64 columns and without RCQR_FLAG_REORTH; otherwise
+ *               ignored.
+ *   grid_mult   cap of the multi-row passes' grids, in workgroups per compute unit (1 .. 8,
+ *               default 2).
+ * rcqr_tune() times every combination (final_mode x grid_mult in {1, 2, 4}) on the caller's V
+ * with `reps` factorizations each (after one warm-up) on the plan's stream, keeps the fastest in
+ * the plan and returns its mean milliseconds through *best_ms (may be NULL).  It synchronises the
+ * stream; Q must not alias V.  rcqr_set_tuning / rcqr_get_tuning store and read the choice
+ * (for callers that cache it per shape).
+ */
+#define RCQR_FINAL_RECOMPUTE 0
+#define RCQR_FINAL_MATERIALIZE 1
+rcqr_status_t rcqr_tune(rcqr_plan_t plan, const double* d_V, int64_t ldv, double* d_Q, int64_t ldq, double* d_R,
+                        int64_t ldr, int32_t reps, float* best_ms);
+rcqr_status_t rcqr_set_tuning(rcqr_plan_t plan, int32_t final_mode, int32_t grid_mult);
+rcqr_status_t rcqr_get_tuning(rcqr_plan_t plan, int32_t* final_mode, int32_t* grid_mult);
+
+/*
  * HIP graphs.  rcqr_graph_create() records one factorization of the given V into Q and R
  * (method RCQR_METHOD_RAND_CHOLQR = rcqr_factor, RCQR_METHOD_CHOLQR2, RCQR_METHOD_SCHOLQR3) by
  * stream capture on the plan's stream and instantiates it; nothing runs during the capture.

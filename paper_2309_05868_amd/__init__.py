@@ -23,6 +23,7 @@ MAX_N = 128  # largest number of columns the kernels accept
 # plan flags (include/rcqr.h): single-precision sketch, BF16 Gaussian product, second Cholesky QR
 FLAG_SKETCH_FP32, FLAG_GEMM_BF16, FLAG_REORTH = 1, 2, 4
 METHODS = {"rand_cholqr": 0, "cholqr2": 1, "scholqr3": 2}
+FINAL_RECOMPUTE, FINAL_MATERIALIZE = 0, 1
 
 _lib = None
 
@@ -44,6 +45,9 @@ _SIGNATURES = {
     "rcqr_gaussian_block": (_c_i32, [_c_p, _c_i64, _c_i64, _c_i64, _c_i64, _c_p]),
     "rcqr_intermediates": (_c_i32, [_c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "rcqr_q0_twice": (_c_i32, [_c_p, _c_p, _c_i64, _c_p, _c_p, _c_i64]),
+    "rcqr_tune": (_c_i32, [_c_p, _c_p, _c_i64, _c_p, _c_i64, _c_p, _c_i64, _c_i32, ctypes.POINTER(ctypes.c_float)]),
+    "rcqr_set_tuning": (_c_i32, [_c_p, _c_i32, _c_i32]),
+    "rcqr_get_tuning": (_c_i32, [_c_p, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32)]),
     "rcqr_graph_create": (_c_i32, [_c_p, _c_i32, _c_p, _c_i64, _c_p, _c_i64, _c_p, _c_i64, ctypes.POINTER(_c_p)]),
     "rcqr_graph_launch": (_c_i32, [_c_p]),
     "rcqr_graph_destroy": (_c_i32, [_c_p]),
@@ -183,6 +187,24 @@ class Plan:
         st, col = self.info()
         if st != OK:
             raise RcqrError(st, what, col)
+
+    def tune(self, V, reps=3):
+        """Time the result-neutral launch choices on V and keep the fastest; returns
+        (final_mode, grid_mult, ms per factorization).  Synchronises the plan's stream."""
+        Q, R = self._outputs(V, None, None)
+        best = ctypes.c_float()
+        _check(lib().rcqr_tune(self._h, ctypes.c_void_p(V.data_ptr()), V.stride(0), ctypes.c_void_p(Q.data_ptr()), Q.stride(0),
+                               ctypes.c_void_p(R.data_ptr()), R.stride(0), int(reps), ctypes.byref(best)), "rcqr_tune")
+        mode, mult = self.tuning()
+        return mode, mult, float(best.value)
+
+    def tuning(self):
+        mode, mult = _c_i32(), _c_i32()
+        _check(lib().rcqr_get_tuning(self._h, ctypes.byref(mode), ctypes.byref(mult)), "rcqr_get_tuning")
+        return mode.value, mult.value
+
+    def set_tuning(self, final_mode, grid_mult):
+        _check(lib().rcqr_set_tuning(self._h, int(final_mode), int(grid_mult)), "rcqr_set_tuning")
 
     def graph(self, V, Q=None, R=None, method="rand_cholqr"):
         """Capture one factorization of V into (Q, R) as a HIP graph; returns a Graph whose

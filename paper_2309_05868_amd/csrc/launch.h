@@ -87,13 +87,17 @@ hipError_t launch_trsm_gram(int np, const double* V, int64_t m, int n, int64_t l
                             double* gpart, double* q0, int64_t ldq, hipStream_t s);
 // Device properties the launchers read (multiprocessor count), queried once, before any capture.
 hipError_t prepare_stream_launches();
+// grid_mult: workgroups per CU cap of the multi-row kernels (a launch-shape knob; never changes results).
 hipError_t launch_final(int np, bool apply_r1, const double* V, int64_t m, int n, int64_t ldv, const double* r0pk,
-                        const double* r1pk, const int32_t* info, double* Q, int64_t ldq, hipStream_t s);
+                        const double* r1pk, const int32_t* info, double* Q, int64_t ldq, hipStream_t s, int grid_mult = 2);
+// Q = Q0 R1^{-1} in place for a stored Q0 (np <= 64), bitwise the same as launch_final's second step.
+hipError_t launch_apply_rinv(int np, double* Q, int64_t m, int n, int64_t ldq, const double* r1pk, const int32_t* info, int grid_mult,
+                             hipStream_t s);
 
 // --- stream128.hip (65..128 columns; factor in the blocked packed format) --------------------
 // out = in R^{-1} row by row (out may alias in with the same leading dimension).
 hipError_t launch_solve128(const double* in, int64_t m, int n, int64_t ldin, const double* rbk, const int32_t* info, double* out,
-                           int64_t ldout, hipStream_t s);
+                           int64_t ldout, hipStream_t s, int grid_mult = 2);
 // Gram partials of Q0 (kGramBlocks compact partials of 36 upper 16x16 blocks).
 hipError_t launch_syrk128(const double* Q0, int64_t m, int n, int64_t ldq, const int32_t* info, double* gpart, hipStream_t s);
 

@@ -138,6 +138,9 @@ struct rcqr_plan_s {
   uint32_t flags;
   hipStream_t stream;
   char* ws;
+  // launch choices that never change results (set by rcqr_tune or rcqr_set_tuning)
+  int final_mode;  // RCQR_FINAL_RECOMPUTE or RCQR_FINAL_MATERIALIZE
+  int grid_mult;   // workgroups-per-CU cap of the multi-row passes
   // per-phase timing: a ring of `cap` steps, kPhases + 1 events each
   int cap;
   int recorded;
@@ -237,14 +240,16 @@ static rcqr_status_t run_sketch(rcqr_plan_t p, const double* V, int64_t ldv) {
 
 // G = (V Rp^{-1})^T (V Rp^{-1}) into the compact buffer.  Up to 64 columns Q0 is never stored
 // (the final pass recomputes it); for 65..128 columns Q0 is written into Q and read back.
-static rcqr_status_t run_gram(rcqr_plan_t p, const double* V, int64_t ldv, const double* rpk, double* Q, int64_t ldq) {
+static rcqr_status_t run_gram(rcqr_plan_t p, const double* V, int64_t ldv, const double* rpk, double* Q, int64_t ldq,
+                              bool store_q0 = false) {
   const Shape& sh = p->sh;
   const int len = gram_compact_len(sh.np);
   const int32_t* info = p->at<int32_t>(p->L.info);
   if (sh.np <= 64) {
-    RCQR_TRY(launch_trsm_gram(sh.np, V, sh.m, (int)sh.n, ldv, rpk, info, p->at<double>(p->L.gpart), nullptr, 0, p->stream));
+    RCQR_TRY(launch_trsm_gram(sh.np, V, sh.m, (int)sh.n, ldv, rpk, info, p->at<double>(p->L.gpart), store_q0 ? Q : nullptr,
+                              store_q0 ? ldq : 0, p->stream));
   } else {
-    RCQR_TRY(launch_solve128(V, sh.m, (int)sh.n, ldv, rpk, info, Q, ldq, p->stream));
+    RCQR_TRY(launch_solve128(V, sh.m, (int)sh.n, ldv, rpk, info, Q, ldq, p->stream, p->grid_mult));
     RCQR_TRY(launch_syrk128(Q, sh.m, (int)sh.n, ldq, info, p->at<double>(p->L.gpart), p->stream));
   }
   RCQR_TRY(launch_reduce_parts(p->at<double>(p->L.gpart), kGramBlocks, len, len, p->at<double>(p->L.gc), p->stream));
@@ -257,9 +262,9 @@ static rcqr_status_t run_final(rcqr_plan_t p, const double* V, int64_t ldv, cons
   const Shape& sh = p->sh;
   const int32_t* info = p->at<int32_t>(p->L.info);
   if (sh.np <= 64) {
-    RCQR_TRY(launch_final(sh.np, true, V, sh.m, (int)sh.n, ldv, r0pk, r1pk, info, Q, ldq, p->stream));
+    RCQR_TRY(launch_final(sh.np, true, V, sh.m, (int)sh.n, ldv, r0pk, r1pk, info, Q, ldq, p->stream, p->grid_mult));
   } else {
-    RCQR_TRY(launch_solve128(Q, sh.m, (int)sh.n, ldq, r1pk, info, Q, ldq, p->stream));
+    RCQR_TRY(launch_solve128(Q, sh.m, (int)sh.n, ldq, r1pk, info, Q, ldq, p->stream, p->grid_mult));
   }
   return RCQR_OK;
 }
@@ -302,6 +307,8 @@ rcqr_status_t rcqr_plan(rcqr_plan_t* plan, int64_t m, int64_t n, int64_t s1, int
   p->flags = flags;
   p->stream = reinterpret_cast<hipStream_t>(stream);
   p->ws = reinterpret_cast<char*>(d_workspace);
+  p->final_mode = RCQR_FINAL_RECOMPUTE;
+  p->grid_mult = 2;
   p->cap = 0;
   p->recorded = 0;
   p->ev = nullptr;
@@ -395,8 +402,10 @@ rcqr_status_t rcqr_factor(rcqr_plan_t p, const double* V, int64_t ldv, double* Q
   // Algorithm 1, step 2: R0 = hhqr(W)
   if ((fp32 ? run_householder<float>(p) : run_householder<double>(p)) != RCQR_OK) return RCQR_E_HIP;
   if (mark(p, 3) != RCQR_OK) return RCQR_E_HIP;
-  // Algorithm 1, step 3 + Algorithm 2, step 1: Q0 = V R0^{-1}, G = Q0^T Q0
-  if (run_gram(p, V, ldv, p->at<double>(L.r0pk), Q, ldq) != RCQR_OK) return RCQR_E_HIP;
+  // Algorithm 1, step 3 + Algorithm 2, step 1: Q0 = V R0^{-1}, G = Q0^T Q0 (Q0 stored in Q when
+  // materialising: the same rows the final pass would recompute)
+  const bool mat = p->final_mode == RCQR_FINAL_MATERIALIZE && sh.np <= 64 && !reorth;
+  if (run_gram(p, V, ldv, p->at<double>(L.r0pk), Q, ldq, mat) != RCQR_OK) return RCQR_E_HIP;
   if (mark(p, 4) != RCQR_OK) return RCQR_E_HIP;
   // Algorithm 2, step 2 and Algorithm 3, step 3: R1 = chol(G), R = R1 R0
   double* r_first = reorth ? p->at<double>(L.rtmp) : R;
@@ -415,7 +424,11 @@ rcqr_status_t rcqr_factor(rcqr_plan_t p, const double* V, int64_t ldv, double* Q
   }
   if (mark(p, 6) != RCQR_OK) return RCQR_E_HIP;
   // Algorithm 2, step 3 on Q0 (or Q1): Q = Q0 R1^{-1}
-  if (run_final(p, V, ldv, first_pk, p->at<double>(L.r1pk), Q, ldq) != RCQR_OK) return RCQR_E_HIP;
+  if (mat) {
+    RCQR_TRY(launch_apply_rinv(sh.np, Q, sh.m, n, ldq, p->at<double>(L.r1pk), info, p->grid_mult, s));
+  } else if (run_final(p, V, ldv, first_pk, p->at<double>(L.r1pk), Q, ldq) != RCQR_OK) {
+    return RCQR_E_HIP;
+  }
   if (mark(p, 7) != RCQR_OK) return RCQR_E_HIP;
   if (p->cap > 0) ++p->recorded;
   return RCQR_OK;
@@ -519,6 +532,65 @@ rcqr_status_t rcqr_intermediates(rcqr_plan_t p, double* d_W1, double* d_W, doubl
       RCQR_TRY(hipMemcpyAsync(e.dst, p->ws + e.off, e.bytes, hipMemcpyDeviceToDevice, p->stream));
   }
   return RCQR_OK;
+}
+
+rcqr_status_t rcqr_set_tuning(rcqr_plan_t p, int32_t final_mode, int32_t grid_mult) {
+  if (p == nullptr || (final_mode != RCQR_FINAL_RECOMPUTE && final_mode != RCQR_FINAL_MATERIALIZE) || grid_mult < 1 ||
+      grid_mult > 8)
+    return RCQR_E_INVALID;
+  p->final_mode = final_mode;
+  p->grid_mult = grid_mult;
+  return RCQR_OK;
+}
+
+rcqr_status_t rcqr_get_tuning(rcqr_plan_t p, int32_t* final_mode, int32_t* grid_mult) {
+  if (p == nullptr || final_mode == nullptr || grid_mult == nullptr) return RCQR_E_INVALID;
+  *final_mode = p->final_mode;
+  *grid_mult = p->grid_mult;
+  return RCQR_OK;
+}
+
+rcqr_status_t rcqr_tune(rcqr_plan_t p, const double* V, int64_t ldv, double* Q, int64_t ldq, double* R, int64_t ldr, int32_t reps,
+                        float* best_ms) {
+  const rcqr_status_t st = check_io(p, V, ldv, Q, ldq, R, ldr);
+  if (st != RCQR_OK) return st;
+  if ((const void*)Q == (const void*)V || reps < 1 || reps > 1000) return RCQR_E_INVALID;  // V must survive the trials
+  const int modes = (p->sh.np <= 64 && !(p->flags & RCQR_FLAG_REORTH)) ? 2 : 1;
+  const int mults[3] = {1, 2, 4};
+  const int cap = p->cap;
+  p->cap = 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  rcqr_status_t out = RCQR_OK;
+  float best = 0.f;
+  int best_mode = p->final_mode, best_mult = p->grid_mult;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) out = RCQR_E_HIP;
+  for (int mo = 0; mo < modes && out == RCQR_OK; ++mo) {
+    for (int k = 0; k < 3 && out == RCQR_OK; ++k) {
+      p->final_mode = mo;
+      p->grid_mult = mults[k];
+      if (rcqr_factor(p, V, ldv, Q, ldq, R, ldr) != RCQR_OK) out = RCQR_E_HIP;  // warm-up
+      if (out == RCQR_OK && hipEventRecord(e0, p->stream) != hipSuccess) out = RCQR_E_HIP;
+      for (int r = 0; r < reps && out == RCQR_OK; ++r)
+        if (rcqr_factor(p, V, ldv, Q, ldq, R, ldr) != RCQR_OK) out = RCQR_E_HIP;
+      float ms = 0.f;
+      if (out == RCQR_OK && (hipEventRecord(e1, p->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        out = RCQR_E_HIP;
+      ms /= reps;
+      if (out == RCQR_OK && (best == 0.f || ms < best)) {
+        best = ms;
+        best_mode = mo;
+        best_mult = mults[k];
+      }
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  p->cap = cap;
+  p->final_mode = best_mode;
+  p->grid_mult = best_mult;
+  if (best_ms) *best_ms = best;
+  return out;
 }
 
 struct rcqr_graph_s {

@@ -224,6 +224,27 @@ __global__ __launch_bounds__(NW * kWave) void final_kernel(const double* __restr
 // Upper 16x16 block (a, b), a <= b, of an NB x NB block grid, numbered row by row.
 __device__ __forceinline__ int upper_blk(int a, int b, int nb) { return a * nb - a * (a - 1) / 2 + (b - a); }
 
+// Row i of R^{-1} in lane i (x R = e_i by the row substitution), stored as the upper 16 x 16
+// blocks of R^{-1} (row-major blocks, upper_blk order) in rib.  One wave.
+template <int NP>
+__device__ __forceinline__ void build_rinv_blocks(const double* __restrict__ Rpk, double* rib, int lane) {
+  constexpr int NB = NP / 16;
+  double x[NP];
+#pragma unroll
+  for (int c = 0; c < NP; ++c) x[c] = (c == lane) ? 1.0 : 0.0;
+  rowsolve<NP>(x, Rpk);
+  if (lane < NP) {
+    const int a = lane / 16;
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+      if (cb >= a) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) rib[upper_blk(a, cb, NB) * 256 + (lane & 15) * 16 + j] = x[16 * cb + j];
+      }
+    }
+  }
+}
+
 // Q = (V R0^{-1}) R1^{-1} with the second step on the matrix cores.  R1 is the Cholesky factor
 // of the Gram matrix of Q0, whose condition number is that of Q0, O(1) (Section 4's remark on
 // kappa of randQR's Q); its inverse is formed accurately and applied as a product, while the
@@ -246,22 +267,7 @@ __global__ __launch_bounds__(NW * kWave) void final_mfma_kernel(const double* __
   if (info[0] != 0) return;
   const int wave = threadIdx.x / kWave, lane = lane_id();
   const int li = lane & 15, lq = lane >> 4;
-  if (wave == 0) {
-    double x[NP];
-#pragma unroll
-    for (int c = 0; c < NP; ++c) x[c] = (c == lane) ? 1.0 : 0.0;
-    rowsolve<NP>(x, R1pk);
-    if (lane < NP) {
-      const int a = lane / 16;
-#pragma unroll
-      for (int cb = 0; cb < NB; ++cb) {
-        if (cb >= a) {
-#pragma unroll
-          for (int j = 0; j < 16; ++j) rib[upper_blk(a, cb, NB) * 256 + (lane & 15) * 16 + j] = x[16 * cb + j];
-        }
-      }
-    }
-  }
+  if (wave == 0) build_rinv_blocks<NP>(R1pk, rib, lane);
   __syncthreads();
   double (*s)[NP + 1] = st[wave];
   const int64_t ntiles = (m + kWave - 1) / kWave;
@@ -393,6 +399,52 @@ __global__ __launch_bounds__(NW * kWave) void solve_hi_kernel(const double* in, 
   }
 }
 
+// Q = Q0 R1^{-1} in place for a stored Q0 (the materialising alternative to final_mfma_kernel,
+// chosen by the tuner): the MFMA operands are read straight from the Q0 rows (16 rows x 4
+// columns per K-step), the same products in the same order as final_mfma_kernel, so Q is bitwise
+// the same.  Each 16-row block is read completely before it is overwritten.
+template <int NP, bool FULL, int NW>
+__global__ __launch_bounds__(NW * kWave) void apply_rinv_kernel(double* Q, int64_t m, int n, int64_t ldq,
+                                                               const double* __restrict__ R1pk, const int32_t* __restrict__ info) {
+  constexpr int NB = NP / 16;
+  constexpr int NBU = NB * (NB + 1) / 2;
+  __shared__ double rib[NBU * 256];
+  if (info[0] != 0) return;
+  const int wave = threadIdx.x / kWave, lane = lane_id();
+  const int li = lane & 15, lq = lane >> 4;
+  if (wave == 0) build_rinv_blocks<NP>(R1pk, rib, lane);
+  __syncthreads();
+  const int64_t nblk16 = (m + 15) / 16;
+  for (int64_t b16 = (int64_t)blockIdx.x * NW + wave; b16 < nblk16; b16 += (int64_t)gridDim.x * NW) {
+    const int64_t arow = b16 * 16 + li;
+    double a[NP / 4];
+#pragma unroll
+    for (int k = 0; k < NP / 4; ++k) {
+      const int col = 4 * k + lq;
+      a[k] = (arow < m && (FULL || col < n)) ? Q[arow * ldq + col] : 0.0;
+    }
+    d4 acc[NB];
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < NP / 4; ++k) {
+#pragma unroll
+      for (int cb = k / 4; cb < NB; ++cb)
+        acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k], rib[upper_blk(k / 4, cb, NB) * 256 + (4 * (k % 4) + lq) * 16 + li],
+                                                       acc[cb], 0, 0, 0);
+    }
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+      const int col = 16 * cb + li;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t r = b16 * 16 + lq + 4 * e;
+        if (r < m && (FULL || col < n)) Q[r * ldq + col] = acc[cb][e];
+      }
+    }
+  }
+}
+
 static bool full_rows(int np, int n, const void* a, int64_t lda, const void* b, int64_t ldb) {
   const bool al = (reinterpret_cast<uintptr_t>(a) % 16 == 0) && (lda % 2 == 0);
   const bool bl = b == nullptr || ((reinterpret_cast<uintptr_t>(b) % 16 == 0) && (ldb % 2 == 0));
@@ -434,7 +486,7 @@ hipError_t prepare_stream_launches() {
 }
 
 hipError_t launch_final(int np, bool apply_r1, const double* V, int64_t m, int n, int64_t ldv, const double* r0pk,
-                        const double* r1pk, const int32_t* info, double* Q, int64_t ldq, hipStream_t s) {
+                        const double* r1pk, const int32_t* info, double* Q, int64_t ldq, hipStream_t s, int grid_mult) {
   if (m <= 0) return hipSuccess;
   const bool full = full_rows(np, n, V, ldv, Q, ldq);
   const int64_t tiles = (m + kWave - 1) / kWave;
@@ -442,7 +494,7 @@ hipError_t launch_final(int np, bool apply_r1, const double* V, int64_t m, int n
     // eight waves per workgroup, about two workgroups per CU over the whole pass
     constexpr int NW = 8;
     int64_t g = (tiles + NW - 1) / NW;
-    if (g > 2 * final_grid()) g = 2 * final_grid();
+    if (g > (int64_t)grid_mult * final_grid()) g = (int64_t)grid_mult * final_grid();
     const dim3 grid((unsigned)g), block(NW * kWave);
 #define RCQR_FINAL_MFMA(NPV)                                                                                                  \
   if (full)                                                                                                                   \
@@ -479,8 +531,32 @@ hipError_t launch_final(int np, bool apply_r1, const double* V, int64_t m, int n
   return hipGetLastError();
 }
 
+hipError_t launch_apply_rinv(int np, double* Q, int64_t m, int n, int64_t ldq, const double* r1pk, const int32_t* info, int grid_mult,
+                             hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  constexpr int NW = 8;
+  const bool full = full_rows(np, n, Q, ldq, nullptr, 0);
+  const int64_t blocks = (m + 15) / 16;
+  int64_t g = (blocks + NW - 1) / NW;
+  if (g > (int64_t)grid_mult * final_grid()) g = (int64_t)grid_mult * final_grid();
+  const dim3 grid((unsigned)g), block(NW * kWave);
+#define RCQR_APPLY(NPV)                                                                                             \
+  if (full)                                                                                                         \
+    hipLaunchKernelGGL((apply_rinv_kernel<NPV, true, NW>), grid, block, 0, s, Q, m, n, ldq, r1pk, info);          \
+  else                                                                                                              \
+    hipLaunchKernelGGL((apply_rinv_kernel<NPV, false, NW>), grid, block, 0, s, Q, m, n, ldq, r1pk, info);
+  switch (np) {
+    case 16: RCQR_APPLY(16) break;
+    case 32: RCQR_APPLY(32) break;
+    case 64: RCQR_APPLY(64) break;
+    default: return hipErrorInvalidValue;
+  }
+#undef RCQR_APPLY
+  return hipGetLastError();
+}
+
 hipError_t launch_solve128(const double* in, int64_t m, int n, int64_t ldin, const double* rbk, const int32_t* info, double* out,
-                           int64_t ldout, hipStream_t s) {
+                           int64_t ldout, hipStream_t s, int grid_mult) {
   if (m <= 0) return hipSuccess;
   if (n <= 64 || n > 128) return hipErrorInvalidValue;
   // x_lo = v_lo R00^{-1} into the output's first 64 columns (R00 packed leads the blocked format)
@@ -489,7 +565,7 @@ hipError_t launch_solve128(const double* in, int64_t m, int n, int64_t ldin, con
   constexpr int NW = 8;
   const int64_t tiles = (m + kWave - 1) / kWave;
   int64_t g = (tiles + NW - 1) / NW;
-  if (g > 2 * final_grid()) g = 2 * final_grid();
+  if (g > (int64_t)grid_mult * final_grid()) g = (int64_t)grid_mult * final_grid();
   const dim3 grid((unsigned)g), block(NW * kWave);
   const bool full = n == 128 && full_rows(64, 64, in, ldin, out, ldout);
   if (full)

@@ -91,6 +91,18 @@ def test_plan_rejects_bad_arguments_on_host(lib):
         assert lib.rcqr_graph_create(h, 0, p, 16, p, 16, p, 16, ctypes.byref(g)) == rc.E_INVALID
         assert lib.rcqr_graph_create(h, 7, p, 16, p, 16, p, 16, ctypes.byref(g)) == rc.E_INVALID
         assert lib.rcqr_graph_create(h, 0, p, 16, p, 16, p, 16, None) == rc.E_INVALID
+        # tuning knobs: defaults, host-side validation, round trip; rcqr_tune refuses Q aliasing V
+        mode, mult = ctypes.c_int32(), ctypes.c_int32()
+        assert lib.rcqr_get_tuning(h, ctypes.byref(mode), ctypes.byref(mult)) == rc.OK
+        assert (mode.value, mult.value) == (rc.FINAL_RECOMPUTE, 2)
+        assert lib.rcqr_set_tuning(h, 2, 1) == rc.E_INVALID
+        assert lib.rcqr_set_tuning(h, 1, 0) == rc.E_INVALID
+        assert lib.rcqr_set_tuning(h, 1, 9) == rc.E_INVALID
+        assert lib.rcqr_set_tuning(h, rc.FINAL_MATERIALIZE, 4) == rc.OK
+        assert lib.rcqr_get_tuning(h, ctypes.byref(mode), ctypes.byref(mult)) == rc.OK
+        assert (mode.value, mult.value) == (rc.FINAL_MATERIALIZE, 4)
+        assert lib.rcqr_tune(h, p, 16, p, 16, p, 16, 3, None) == rc.E_INVALID
+        assert lib.rcqr_tune(h, p, 16, ctypes.c_void_p(8192), 16, p, 16, 0, None) == rc.E_INVALID
     finally:
         assert lib.rcqr_destroy(h) == rc.OK
     assert lib.rcqr_graph_launch(None) == rc.E_INVALID
