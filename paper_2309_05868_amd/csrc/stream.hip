@@ -150,9 +150,9 @@ __global__ __launch_bounds__(kGramThreads, 1) void trsm_gram_kernel(const double
     double x[NP];
     load_row<NP, FULL>(x, V, row, m, n, ldv);
     rowsolve<NP>(x, R0pk);
-    if (q0 != nullptr && row < m) store_row<NP, FULL>(x, q0, row, n, ldq);
     // transpose 16-column blocks through LDS into MFMA operands:
-    // F[a][s] (lane l) = X[4s + l/16][16a + l%16]
+    // F[a][s] (lane l) = X[4s + l/16][16a + l%16]; when Q0 is stored, it is written from the same
+    // staging, eight lanes per 128-byte row segment
     double F[NB][16];
 #pragma unroll
     for (int a = 0; a < NB; ++a) {
@@ -161,6 +161,24 @@ __global__ __launch_bounds__(kGramThreads, 1) void trsm_gram_kernel(const double
       wave_lds_sync();
 #pragma unroll
       for (int s = 0; s < 16; ++s) F[a][s] = xs[wave][lane & 15][4 * s + (lane >> 4)];
+      if (q0 != nullptr) {
+        const int cp = 2 * (lane & 7);
+        const int col = 16 * a + cp;
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+          const int rr = (lane >> 3) + 8 * it;
+          const int64_t r = t * kWave + rr;
+          if (r < m) {
+            double* dst = q0 + r * ldq + col;
+            if constexpr (FULL) {
+              *reinterpret_cast<double2*>(dst) = double2{xs[wave][cp][rr], xs[wave][cp + 1][rr]};
+            } else {
+              if (col < n) dst[0] = xs[wave][cp][rr];
+              if (col + 1 < n) dst[1] = xs[wave][cp + 1][rr];
+            }
+          }
+        }
+      }
       wave_lds_sync();
     }
 #pragma unroll
