@@ -127,7 +127,7 @@ int gram_compact_len(int np) {
   return nb * (nb + 1) / 2 * 256;
 }
 
-template <int NP, bool FULL>
+template <int NP, bool FULL, bool STORE>
 __global__ __launch_bounds__(kGramThreads, 1) void trsm_gram_kernel(const double* __restrict__ V, int64_t m, int n, int64_t ldv,
                                                                     const double* __restrict__ R0pk,
                                                                     const int32_t* __restrict__ info, double* __restrict__ gpart,
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kGramThreads, 1) void trsm_gram_kernel(const double
       wave_lds_sync();
 #pragma unroll
       for (int s = 0; s < 16; ++s) F[a][s] = xs[wave][lane & 15][4 * s + (lane >> 4)];
-      if (q0 != nullptr) {
+      if constexpr (STORE) {
         const int cp = 2 * (lane & 7);
         const int col = 16 * a + cp;
 #pragma unroll
@@ -473,11 +473,15 @@ hipError_t launch_trsm_gram(int np, const double* V, int64_t m, int n, int64_t l
                             double* gpart, double* q0, int64_t ldq, hipStream_t s) {
   const dim3 grid(kGramBlocks), block(kGramThreads);
   const bool full = full_rows(np, n, V, ldv, q0, ldq);
-#define RCQR_GRAM(NPV)                                                                                                   \
-  if (full)                                                                                                              \
-    hipLaunchKernelGGL((trsm_gram_kernel<NPV, true>), grid, block, 0, s, V, m, n, ldv, r0pk, info, gpart, q0, ldq);    \
-  else                                                                                                                   \
-    hipLaunchKernelGGL((trsm_gram_kernel<NPV, false>), grid, block, 0, s, V, m, n, ldv, r0pk, info, gpart, q0, ldq);
+#define RCQR_GRAM(NPV)                                                                                                          \
+  if (full && q0)                                                                                                               \
+    hipLaunchKernelGGL((trsm_gram_kernel<NPV, true, true>), grid, block, 0, s, V, m, n, ldv, r0pk, info, gpart, q0, ldq);      \
+  else if (full)                                                                                                                \
+    hipLaunchKernelGGL((trsm_gram_kernel<NPV, true, false>), grid, block, 0, s, V, m, n, ldv, r0pk, info, gpart, q0, ldq);     \
+  else if (q0)                                                                                                                  \
+    hipLaunchKernelGGL((trsm_gram_kernel<NPV, false, true>), grid, block, 0, s, V, m, n, ldv, r0pk, info, gpart, q0, ldq);     \
+  else                                                                                                                          \
+    hipLaunchKernelGGL((trsm_gram_kernel<NPV, false, false>), grid, block, 0, s, V, m, n, ldv, r0pk, info, gpart, q0, ldq);
   switch (np) {
     case 16: RCQR_GRAM(16) break;
     case 32: RCQR_GRAM(32) break;
