@@ -17,6 +17,7 @@ timed region), and the CPU oracle timed on a bounded sample of the same workload
   python bench.py --workload mixed     # precision variants, m = 4e6, n = 128, kappa = 1e14
   python bench.py --workload serve     # 4096 requests, continuous batching vs one at a time
   python bench.py --workload latency   # small factorizations, eager vs HIP graph
+  python bench.py --workload sweep     # n in {8, 32, 128} at 1-2 GB of V, kappa 1e2 / 1e8 / 1e15
 """
 
 import argparse
@@ -266,6 +267,71 @@ def serve_workload(args):
     print(json.dumps(line), flush=True)
 
 
+# bandwidth sweep: about 1-2 GB of V per n, three condition numbers, s1 = 2 n^2, s2 = 4 n
+SWEEP_SHAPES = [(16_777_216, 8), (8_388_608, 32), (2_097_152, 128)]
+SWEEP_KAPPAS = [1e2, 1e8, 1e15]
+
+
+def sweep_workload(args):
+    """Per n: QR/s, algorithmic GB/s (32 m n bytes), Gram-pass FP64 rate against the FP64 peak
+    (m n (n + 1) flops of the Gram matrix over the Gram phase), accuracy, for three kappa."""
+    import numpy as np
+    import torch
+
+    import paper_2309_05868_amd as rc
+    import synth
+
+    dev = torch.device("cuda:0")
+    out = []
+    for m, n in SWEEP_SHAPES:
+        log(f"bench: sweep basis {m} x {n}")
+        U, _, W = synth.make_factors(m, n, 1.0, seed=200 + n)
+        Ud = torch.from_numpy(U).to(dev)
+        del U
+        Wt = torch.from_numpy(np.ascontiguousarray(W.T)).to(dev)
+        s1, s2 = 2 * n * n, 4 * n
+        for kappa in SWEEP_KAPPAS:
+            sig = torch.from_numpy(synth.singular_values(n, kappa)).to(dev)
+            V = (Ud * sig) @ Wt
+            Q = torch.empty_like(V)
+            R = torch.empty((n, n), dtype=torch.float64, device=dev)
+            with rc.Plan(m, n, s1, s2, seed=200 + n, device=dev) as plan:
+                for _ in range(args.warmup):
+                    plan.factor(V, Q, R, check=False)
+                plan.set_timing(args.steps)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(plan.stream)
+                for _ in range(args.steps):
+                    plan.factor(V, Q, R, check=False)
+                e1.record(plan.stream)
+                e1.synchronize()
+                ms = e0.elapsed_time(e1) / args.steps
+                ph = plan.phase_times()
+                st, col = plan.info()
+            rec = {"m": m, "n": n, "kappa": kappa, "s1": s1, "s2": s2, "ms_per_qr": round(ms, 4), "qr_per_s": round(1e3 / ms, 2),
+                   "gbps_algorithmic": round(32.0 * m * n / (ms * 1e-3) / 1e9, 1), "status": st,
+                   "phase_ms": {k: round(v, 4) for k, v in ph.items()}}
+            gram_flops = float(m) * n * (n + 1)
+            rec["gram_fp64_tflops"] = round(gram_flops / (ph["trsm_gram"] * 1e-3) / 1e12, 2)
+            rec["gram_frac_of_fp64_peak"] = round(rec["gram_fp64_tflops"] / FP64_PEAK_TFLOPS, 4)
+            if st == 0:
+                eye = torch.eye(n, dtype=torch.float64, device=dev)
+                rec["orth_error"] = torch.linalg.norm(eye - gram_accurate(Q)).item()
+                rec["residual"] = (torch.linalg.norm(V - Q @ R) / torch.linalg.norm(V)).item()
+                rec["within_target"] = bool(max(rec["orth_error"], rec["residual"]) <= 10 * n * U_PAPER)
+            out.append(rec)
+            log(f"bench: sweep n={n} kappa={kappa:.0e}: {rec['ms_per_qr']} ms, {rec['gbps_algorithmic']} GB/s")
+            del V, Q
+        del Ud
+        torch.cuda.empty_cache()
+    line = {"metric": METRIC, "value": None, "unit": "QR/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "rand_cholQR bandwidth sweep: (m, n) = (16777216, 8), (8388608, 32), (2097152, 128); "
+                                   "kappa 1e2, 1e8, 1e15; s1 = 2 n^2, s2 = 4 n"},
+            "runs": out}
+    print(json.dumps(line), flush=True)
+
+
 LATENCY_SHAPES = [dict(m=10_000, n=16, kappa=1e4, s1=512, s2=64, seed=0),
                   dict(m=100_000, n=64, kappa=1e8, s1=8192, s2=256, seed=0)]
 
@@ -359,10 +425,10 @@ def main():
     ap.add_argument("--tune", action="store_true", help="run rcqr_tune (result-neutral launch choices) before warm-up")
     ap.add_argument("--comparator-steps", type=int, default=5)
     ap.add_argument("--cpu-sample-rows", type=int, default=100_000)
-    ap.add_argument("--workload", choices=["default", "mixed", "serve", "latency"], default="default",
+    ap.add_argument("--workload", choices=["default", "mixed", "serve", "latency", "sweep"], default="default",
                     help="mixed: FP32/BF16 preconditioner variants against FP64 at m=4e6, n=128, kappa=1e14; "
                          "serve: continuous batching of 4096 Poisson-arriving requests; "
-                         "latency: small factorizations, eager vs HIP graph")
+                         "latency: small factorizations, eager vs HIP graph; sweep: n in {8, 32, 128} at 1-2 GB")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-budget-gb", type=int, default=64)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -400,6 +466,9 @@ def main():
         return
     if args.workload == "latency":
         latency_workload(args)
+        return
+    if args.workload == "sweep":
+        sweep_workload(args)
         return
     wl = WORKLOAD
     m, n = wl["m"], wl["n"]

@@ -440,10 +440,23 @@ __global__ __launch_bounds__(256) void countsketch_lds_kernel(const double* __re
     }
     wave_lds_sync();
     const int rows = (int)((r_end - base) < kCsChunk ? (r_end - base) : kCsChunk);
-    for (int b0 = 0; b0 < rows; b0 += RB) {
+    // the rows of a sub-chunk are loaded together (NBS independent loads per lane in flight),
+    // then added batch by batch in row order
+    constexpr int SCR = NPL <= 16 ? 128 : 64;  // rows per sub-chunk
+    constexpr int NBS = SCR / RB;              // batches per sub-chunk
+    for (int s0 = 0; s0 < rows; s0 += SCR) {
+    T vv[NBS];
+#pragma unroll
+    for (int k = 0; k < NBS; ++k) {
+      const int rq = s0 + k * RB + q;
+      vv[k] = (T)((rq < rows && c < n) ? V[(base + rq) * ldv + c] : 0.0);
+    }
+#pragma unroll
+    for (int k = 0; k < NBS; ++k) {
+      const int b0 = s0 + k * RB;
       const int rq = b0 + q;
       const bool valid = rq < rows && c < n;
-      T v = (T)(valid ? V[(base + rq) * ldv + c] : 0.0);
+      T v = vv[k];
       const uint32_t code = rq < rows ? codes[wave][rq] : 0u;
       if (code & 1u) v = -v;
       const uint32_t bkt = code >> 1;
@@ -464,6 +477,7 @@ __global__ __launch_bounds__(256) void countsketch_lds_kernel(const double* __re
         if (valid) mine[bkt * NPL + c] += v;
       }
       wave_lds_sync();
+    }
     }
   }
   __syncthreads();
@@ -501,90 +515,20 @@ hipError_t launch_countsketch_lds(const double* V, int64_t ldv, int64_t m, int n
 }
 
 // ------------------------------------------------------------------------------------------
-// Gaussian sketch GEMM (split over s1): Wpart[kc] = S2[:, chunk] W1[chunk, :].
+// Gaussian sketch GEMM on the matrix cores, split over s1: Wpart[kc] = S2[:, chunk] W1[chunk, :],
+// the partial products of the s1 chunks summed afterwards in a fixed order.  S2 tiles are drawn
+// on the fly from the counter-based generator and never stored in HBM.  Wave w owns S2 rows
+// 16w..16w+15 of the workgroup's 64-row block and every 16-column block of W.  Operand lanes:
+// row/column = lane % 16, k group = lane / 16 (the same k order on both operands, so any k
+// permutation inside the instruction cancels).
+//   * single-precision sketch: S2 entries are the FP64 contract values rounded to FP32 (for the
+//     BF16 variant both operands rounded on to BF16), v_mfma_f32_16x16x4f32 (8 per 32-wide k
+//     step) or v_mfma_f32_16x16x32_bf16 (one per step), FP32 accumulation; result lane l,
+//     element e: row 4 (l / 16) + e, column l % 16;
+//   * FP64 sketch: v_mfma_f64_16x16x4f64, FP64 throughout; result lane l, element e: row
+//     l / 16 + 4e, column l % 16.
 // ------------------------------------------------------------------------------------------
 constexpr int kGemmRows = 64;  // rows of S2 (and W) per workgroup
-constexpr int kGemmK = 16;     // k-step held in LDS
-
-template <int NPL>
-__global__ __launch_bounds__(256) void gauss_gemm_kernel(const double* __restrict__ W1, int n, int64_t s1, int64_t s2, uint64_t seed,
-                                                         double scale, int64_t kc_len, double* __restrict__ wpart) {
-  __shared__ double st[kGemmK][kGemmRows + 1];  // S2 tile [k][j]
-  __shared__ double wt[kGemmK][NPL];            // W1 tile [k][c]
-  constexpr int CPT = NPL / 4;                  // columns per thread
-  const int t = threadIdx.x;
-  const int jl = t % kGemmRows, cg = t / kGemmRows;
-  const int64_t kc = blockIdx.x, rb = blockIdx.y;
-  const int64_t k_beg = kc * kc_len;
-  const int64_t k_end = k_beg + kc_len < s1 ? k_beg + kc_len : s1;
-  double acc[CPT];
-#pragma unroll
-  for (int i = 0; i < CPT; ++i) acc[i] = 0.0;
-  for (int64_t k0 = k_beg; k0 < k_end; k0 += kGemmK) {
-    {  // S2 entries: thread -> (kk, j-block of 4)
-      const int kk = t % kGemmK, jb = t / kGemmK;  // jb in 0..15
-      const int64_t k = k0 + kk;
-      const int64_t jblk = rb * (kGemmRows / 4) + jb;
-      double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
-      if (k < k_end) {
-        const Block4 y = philox4x64_10((uint64_t)k, (uint64_t)jblk, 0, kTagGaussian, seed, 0);
-        box_muller(y.y0, y.y1, z0, z1);
-        box_muller(y.y2, y.y3, z2, z3);
-      }
-      const int64_t j = 4 * jblk;
-      st[kk][4 * jb + 0] = (k < k_end && j + 0 < s2) ? z0 * scale : 0.0;
-      st[kk][4 * jb + 1] = (k < k_end && j + 1 < s2) ? z1 * scale : 0.0;
-      st[kk][4 * jb + 2] = (k < k_end && j + 2 < s2) ? z2 * scale : 0.0;
-      st[kk][4 * jb + 3] = (k < k_end && j + 3 < s2) ? z3 * scale : 0.0;
-    }
-    for (int i = t; i < kGemmK * NPL; i += 256) {
-      const int kk = i / NPL, c = i % NPL;
-      const int64_t k = k0 + kk;
-      wt[kk][c] = (k < k_end && c < n) ? W1[k * n + c] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < kGemmK; ++kk) {
-      const double sv = st[kk][jl];
-#pragma unroll
-      for (int i = 0; i < CPT; ++i) acc[i] = __builtin_fma(sv, wt[kk][cg + 4 * i], acc[i]);
-    }
-    __syncthreads();
-  }
-  const int64_t j = rb * kGemmRows + jl;
-  if (j < s2) {
-    double* out = wpart + (kc * s2 + j) * n;
-#pragma unroll
-    for (int i = 0; i < CPT; ++i) {
-      const int c = cg + 4 * i;
-      if (c < n) out[c] = acc[i];
-    }
-  }
-}
-
-hipError_t launch_gauss_gemm(const double* W1, int n, int64_t s1, int64_t s2, uint64_t seed, double scale, int64_t kc_len,
-                             int64_t nkc, double* wpart, hipStream_t s) {
-  const dim3 grid((unsigned)nkc, (unsigned)((s2 + kGemmRows - 1) / kGemmRows)), block(256);
-  const int npl = n <= 32 ? 32 : n <= 64 ? 64 : 128;
-  if (npl == 32)
-    hipLaunchKernelGGL(gauss_gemm_kernel<32>, grid, block, 0, s, W1, n, s1, s2, seed, scale, kc_len, wpart);
-  else if (npl == 64)
-    hipLaunchKernelGGL(gauss_gemm_kernel<64>, grid, block, 0, s, W1, n, s1, s2, seed, scale, kc_len, wpart);
-  else
-    hipLaunchKernelGGL(gauss_gemm_kernel<128>, grid, block, 0, s, W1, n, s1, s2, seed, scale, kc_len, wpart);
-  return hipGetLastError();
-}
-
-// ------------------------------------------------------------------------------------------
-// Gaussian sketch GEMM of the single-precision sketch on the matrix cores, split over s1 like
-// the FP64 kernel: Wpart[kc] = S2[:, chunk] W1[chunk, :] with FP32 accumulation.  S2 entries are
-// the FP64 contract values rounded to FP32 (and, for the BF16 variant, both operands rounded
-// on to BF16).  Wave w owns S2 rows 16w..16w+15 of the workgroup's 64-row block and every
-// 16-column block of W: v_mfma_f32_16x16x4f32 (8 per 32-wide k step) or
-// v_mfma_f32_16x16x32_bf16 (one per step).  Operand lanes: row/column = lane % 16, k group =
-// lane / 16 (the same k order on both operands, so any k permutation of the instruction cancels).
-// Result lane l, element e: row 4 (l / 16) + e, column l % 16.
-// ------------------------------------------------------------------------------------------
 constexpr int kMmK = 32;  // k step of the matrix-core kernel
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -681,6 +625,86 @@ hipError_t launch_gauss_mfma(const float* W1, int n, int64_t s1, int64_t s2, uin
   RCQR_GAUSS_MFMA(64)
   RCQR_GAUSS_MFMA(128)
 #undef RCQR_GAUSS_MFMA
+  return hipGetLastError();
+}
+
+// FP64 product: 8 v_mfma_f64_16x16x4f64 per 32-wide k step and 16-column block.
+template <int NP>
+__global__ __launch_bounds__(256) void gauss_mfma64_kernel(const double* __restrict__ W1, int n, int64_t s1, int64_t s2, uint64_t seed,
+                                                           double scale, int64_t kc_len, double* __restrict__ wpart) {
+  __shared__ double st[kGemmRows][kMmK + 1];  // S2 tile, [row j][k]
+  __shared__ double wt[NP][kMmK + 1];         // W1 tile transposed, [column c][k]
+  constexpr int NCB = NP / 16;
+  const int t = threadIdx.x, wave = t / kWave, lane = lane_id();
+  const int li = lane % 16, lq = lane / 16;
+  const int64_t kc = blockIdx.x, rb = blockIdx.y;
+  const int64_t k_beg = kc * kc_len;
+  const int64_t k_end = k_beg + kc_len < s1 ? k_beg + kc_len : s1;
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  d4 acc[NCB];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t k0 = k_beg; k0 < k_end; k0 += kMmK) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {  // 512 Philox blocks: (k, block of 4 rows)
+      const int idx = t + 256 * h;
+      const int kk = idx % kMmK, jb = idx / kMmK;
+      const int64_t k = k0 + kk;
+      const int64_t jblk = rb * (kGemmRows / 4) + jb;
+      double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
+      if (k < k_end) {
+        const Block4 y = philox4x64_10((uint64_t)k, (uint64_t)jblk, 0, kTagGaussian, seed, 0);
+        box_muller(y.y0, y.y1, z0, z1);
+        box_muller(y.y2, y.y3, z2, z3);
+      }
+      const int64_t j = 4 * jblk;
+      const bool kin = k < k_end;
+      st[4 * jb + 0][kk] = (kin && j + 0 < s2) ? z0 * scale : 0.0;
+      st[4 * jb + 1][kk] = (kin && j + 1 < s2) ? z1 * scale : 0.0;
+      st[4 * jb + 2][kk] = (kin && j + 2 < s2) ? z2 * scale : 0.0;
+      st[4 * jb + 3][kk] = (kin && j + 3 < s2) ? z3 * scale : 0.0;
+    }
+    for (int i = t; i < kMmK * NP; i += 256) {
+      const int kk = i / NP, c = i % NP;
+      const int64_t k = k0 + kk;
+      wt[c][kk] = (k < k_end && c < n) ? W1[k * n + c] : 0.0;
+    }
+    __syncthreads();
+    const double* arow = st[16 * wave + li];
+#pragma unroll
+    for (int ks = 0; ks < kMmK / 4; ++ks) {
+      const double a = arow[4 * ks + lq];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, wt[16 * cb + li][4 * ks + lq], acc[cb], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) {
+    const int c = 16 * cb + li;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t j = rb * kGemmRows + 16 * wave + lq + 4 * e;
+      if (j < s2 && c < n) wpart[(kc * s2 + j) * n + c] = acc[cb][e];
+    }
+  }
+}
+
+template <int NP>
+static void launch_gauss64(dim3 grid, const double* W1, int n, int64_t s1, int64_t s2, uint64_t seed, double scale, int64_t kc_len,
+                           double* wpart, hipStream_t s) {
+  hipLaunchKernelGGL((gauss_mfma64_kernel<NP>), grid, dim3(256), 0, s, W1, n, s1, s2, seed, scale, kc_len, wpart);
+}
+
+hipError_t launch_gauss_gemm(const double* W1, int n, int64_t s1, int64_t s2, uint64_t seed, double scale, int64_t kc_len,
+                             int64_t nkc, double* wpart, hipStream_t s) {
+  if (kc_len % kMmK != 0) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)nkc, (unsigned)((s2 + kGemmRows - 1) / kGemmRows));
+  const int np = n <= 16 ? 16 : n <= 32 ? 32 : n <= 64 ? 64 : 128;
+  if (np == 16) launch_gauss64<16>(grid, W1, n, s1, s2, seed, scale, kc_len, wpart, s);
+  else if (np == 32) launch_gauss64<32>(grid, W1, n, s1, s2, seed, scale, kc_len, wpart, s);
+  else if (np == 64) launch_gauss64<64>(grid, W1, n, s1, s2, seed, scale, kc_len, wpart, s);
+  else launch_gauss64<128>(grid, W1, n, s1, s2, seed, scale, kc_len, wpart, s);
   return hipGetLastError();
 }
 
