@@ -28,7 +28,7 @@ hipError_t launch_bucket_gather(const double* V, int64_t ldv, int64_t m, int n, 
 hipError_t launch_bucket_gather(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, const uint32_t* offsets,
                                 const uint32_t* entries, float* W1, hipStream_t s);
 // Small-s1 CountSketch: per-wave LDS copies of W1; writes one partial W1 per workgroup.
-int countsketch_lds_parts(int64_t m);
+int countsketch_lds_parts(int64_t m, int64_t s1, int n);
 bool countsketch_lds_fits(int64_t s1, int n);
 hipError_t launch_countsketch_lds(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, uint64_t seed,
                                   double* parts, int nparts, hipStream_t s);

@@ -51,7 +51,7 @@ Shape make_shape(int64_t m, int64_t n, int64_t s1, int64_t s2) {
   sh.s2 = s2;
   sh.np = padded_cols(n);
   sh.lds_cs = countsketch_lds_fits(s1, (int)n);
-  sh.cs_parts = sh.lds_cs ? countsketch_lds_parts(m) : 0;
+  sh.cs_parts = sh.lds_cs ? countsketch_lds_parts(m, s1, (int)n) : 0;
   // bucket index: chunks of at least 4096 rows, at most 256, histogram matrix <= 2^26 entries
   int64_t nch = (m + 4095) / 4096;
   if (nch > 256) nch = 256;

@@ -397,14 +397,7 @@ hipError_t launch_bucket_gather(const double* V, int64_t ldv, int64_t m, int n, 
 // Small-s1 CountSketch: per-wave LDS copies of W1 (s1 x NPL), contiguous row chunks.
 // ------------------------------------------------------------------------------------------
 constexpr int kCsLdsDoubles = 4096;  // s1 * NPL limit (4 waves x 32 KiB)
-constexpr int kCsParts = 512;         // workgroups (and partial copies of W1)
 constexpr int kCsChunk = 256;         // rows hashed at once by one wave
-
-int countsketch_lds_parts(int64_t m) {
-  int64_t p = (m + kCsChunk - 1) / kCsChunk;
-  if (p > kCsParts) p = kCsParts;
-  return p < 1 ? 1 : (int)p;
-}
 
 static int npl_of(int n) {
   int p = 8;
@@ -414,10 +407,27 @@ static int npl_of(int n) {
 
 bool countsketch_lds_fits(int64_t s1, int n) { return n <= 64 && s1 * npl_of(n) <= kCsLdsDoubles; }
 
-template <int NPL, class T>
+// Per-wave capacity of the LDS copies (elements): the smallest of 1024, 2048, 4096 that holds
+// s1 x NPL; smaller copies let more workgroups share a CU (4, 2, 1 at FP64).
+static int cs_cap(int64_t s1, int n) {
+  const int64_t need = s1 * npl_of(n);
+  return need <= 1024 ? 1024 : need <= 2048 ? 2048 : 4096;
+}
+
+// Workgroups (and partial copies of W1): one per 256-row chunk, at most 256 x (workgroups per
+// CU at FP64).  A function of the shape only, so the summation order does not depend on the device.
+int countsketch_lds_parts(int64_t m, int64_t s1, int n) {
+  const int cap = cs_cap(s1, n);
+  const int64_t target = 256 * (cap == 1024 ? 4 : cap == 2048 ? 2 : 1);
+  int64_t p = (m + kCsChunk - 1) / kCsChunk;
+  if (p > target) p = target;
+  return p < 1 ? 1 : (int)p;
+}
+
+template <int NPL, class T, int CAP>
 __global__ __launch_bounds__(256) void countsketch_lds_kernel(const double* __restrict__ V, int64_t ldv, int64_t m, int n, int64_t s1,
                                                               uint64_t seed, T* __restrict__ parts) {
-  __shared__ T w1[4][kCsLdsDoubles];
+  __shared__ T w1[4][CAP];
   __shared__ uint32_t codes[4][kCsChunk];
   constexpr int RB = kWave / NPL;  // rows per batch
   const int wave = threadIdx.x / kWave, lane = lane_id();
@@ -490,15 +500,29 @@ __global__ __launch_bounds__(256) void countsketch_lds_kernel(const double* __re
   }
 }
 
+template <int NPL, class T>
+static void countsketch_lds_cap(int cap, dim3 grid, hipStream_t s, const double* V, int64_t ldv, int64_t m, int n, int64_t s1,
+                                uint64_t seed, T* parts) {
+  const dim3 block(256);
+  if (cap == 1024)
+    hipLaunchKernelGGL((countsketch_lds_kernel<NPL, T, 1024>), grid, block, 0, s, V, ldv, m, n, s1, seed, parts);
+  else if (cap == 2048)
+    hipLaunchKernelGGL((countsketch_lds_kernel<NPL, T, 2048>), grid, block, 0, s, V, ldv, m, n, s1, seed, parts);
+  else
+    hipLaunchKernelGGL((countsketch_lds_kernel<NPL, T, 4096>), grid, block, 0, s, V, ldv, m, n, s1, seed, parts);
+}
+
 template <class T>
 static hipError_t countsketch_lds_any(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, uint64_t seed, T* parts,
                                       int nparts, hipStream_t s) {
-  const dim3 grid((unsigned)nparts), block(256);
+  if (!countsketch_lds_fits(s1, n) || nparts < 1) return hipErrorInvalidValue;
+  const dim3 grid(nparts);
+  const int cap = cs_cap(s1, n);
   switch (npl_of(n)) {
-    case 8: hipLaunchKernelGGL((countsketch_lds_kernel<8, T>), grid, block, 0, s, V, ldv, m, n, s1, seed, parts); break;
-    case 16: hipLaunchKernelGGL((countsketch_lds_kernel<16, T>), grid, block, 0, s, V, ldv, m, n, s1, seed, parts); break;
-    case 32: hipLaunchKernelGGL((countsketch_lds_kernel<32, T>), grid, block, 0, s, V, ldv, m, n, s1, seed, parts); break;
-    case 64: hipLaunchKernelGGL((countsketch_lds_kernel<64, T>), grid, block, 0, s, V, ldv, m, n, s1, seed, parts); break;
+    case 8: countsketch_lds_cap<8, T>(cap, grid, s, V, ldv, m, n, s1, seed, parts); break;
+    case 16: countsketch_lds_cap<16, T>(cap, grid, s, V, ldv, m, n, s1, seed, parts); break;
+    case 32: countsketch_lds_cap<32, T>(cap, grid, s, V, ldv, m, n, s1, seed, parts); break;
+    case 64: countsketch_lds_cap<64, T>(cap, grid, s, V, ldv, m, n, s1, seed, parts); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -746,42 +770,62 @@ hipError_t launch_gaussian_block(int64_t j0, int64_t nj, int64_t k0, int64_t nk,
 // rounding error of each addition is recovered exactly (TwoSum) and added back at the end, so
 // the result does not degrade with the number of partials.
 // ------------------------------------------------------------------------------------------
+// Workgroup: 16 consecutive outputs x 16 groups of parts.  Group g sums parts g, g + 16, g + 32, ...
+// (compensated, increasing p); the 16 group sums are then combined in g order.  The partition
+// depends only on nparts, so the order of every sum is fixed.
 template <class T>
 __global__ __launch_bounds__(256) void reduce_parts_kernel(const T* __restrict__ parts, int64_t nparts, int64_t stride, int64_t len,
                                                            T* __restrict__ out) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x) {
-    T sum = T(0), comp = T(0);
-    int64_t p = 0;
-    for (; p + 8 <= nparts; p += 8) {
-      T v[8];
+  constexpr int E = 16, G = 16;
+  __shared__ T ssum[G][E], scomp[G][E];
+  const int e = threadIdx.x % E, g = threadIdx.x / E;
+  const int64_t i = (int64_t)blockIdx.x * E + e;
+  T sum = T(0), comp = T(0);
+  if (i < len) {
+    int64_t p = g;
+    for (; p + 3 * G < nparts; p += 4 * G) {
+      T v[4];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = parts[(p + u) * stride + i];
+      for (int u = 0; u < 4; ++u) v[u] = parts[(p + u * G) * stride + i];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < 4; ++u) {
         const T t = sum + v[u];
         comp += (fabs(sum) >= fabs(v[u])) ? ((sum - t) + v[u]) : ((v[u] - t) + sum);
         sum = t;
       }
     }
-    for (; p < nparts; ++p) {
+    for (; p < nparts; p += G) {
       const T x = parts[p * stride + i];
       const T t = sum + x;
       comp += (fabs(sum) >= fabs(x)) ? ((sum - t) + x) : ((x - t) + sum);
       sum = t;
     }
-    out[i] = sum + comp;
+  }
+  ssum[g][e] = sum;
+  scomp[g][e] = comp;
+  __syncthreads();
+  if (g == 0 && i < len) {
+    T tot = ssum[0][e], c = scomp[0][e];
+    for (int h = 1; h < G; ++h) {
+      const T x = ssum[h][e];
+      const T t = tot + x;
+      c += (fabs(tot) >= fabs(x)) ? ((tot - t) + x) : ((x - t) + tot);
+      c += scomp[h][e];
+      tot = t;
+    }
+    out[i] = tot + c;
   }
 }
 
 hipError_t launch_reduce_parts(const double* parts, int64_t nparts, int64_t stride, int64_t len, double* out, hipStream_t s) {
   if (len <= 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_parts_kernel<double>, dim3(grid_for(len, 256, 2048)), dim3(256), 0, s, parts, nparts, stride, len, out);
+  hipLaunchKernelGGL(reduce_parts_kernel<double>, dim3((unsigned)((len + 15) / 16)), dim3(256), 0, s, parts, nparts, stride, len, out);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_parts(const float* parts, int64_t nparts, int64_t stride, int64_t len, float* out, hipStream_t s) {
   if (len <= 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_parts_kernel<float>, dim3(grid_for(len, 256, 2048)), dim3(256), 0, s, parts, nparts, stride, len, out);
+  hipLaunchKernelGGL(reduce_parts_kernel<float>, dim3((unsigned)((len + 15) / 16)), dim3(256), 0, s, parts, nparts, stride, len, out);
   return hipGetLastError();
 }
 
