@@ -12,21 +12,28 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream
 hipError_t launch_fill_f64(double* p, int64_t count, double value, hipStream_t s);
 // Bucket index of S1 over `nchunk` contiguous row chunks (one workgroup each):
 //   hash_hist:  codes[i] = (h(i) << 1) | signbit(i); hist[chunk][b] = rows of the chunk in bucket b
-//   colscan:    hist[chunk][b] <- rows of bucket b in earlier chunks; counts[b] = bucket size
+//   colscan:    hist[chunk][b] <- rows of bucket b in earlier chunks; counts[b] = bucket size;
+//               unsorted[b] = 0 (when non-null)
 //   scan:       offsets[0..s1] = exclusive scan of counts (cursor[b] = offsets[b] if non-null)
 //   scatter:    entries[offsets[b] + hist[chunk][b] + k] = (i << 1) | signbit(i)
 int64_t bucket_chunk_rows(int64_t m, int nchunk);
 hipError_t launch_hash_hist(int64_t m, int64_t s1, uint64_t seed, int nchunk, uint32_t* codes, uint32_t* hist, hipStream_t s);
-hipError_t launch_hist_colscan(int nchunk, int64_t s1, uint32_t* hist, uint32_t* counts, hipStream_t s);
+hipError_t launch_hist_colscan(int nchunk, int64_t s1, uint32_t* hist, uint32_t* counts, uint8_t* unsorted, hipStream_t s);
 hipError_t launch_bucket_scan(const uint32_t* counts, int64_t s1, uint32_t* offsets, uint32_t* cursor, hipStream_t s);
+//              when the bucket counters fit in LDS, each chunk's segment of each bucket is then
+//              sorted by row, so every bucket lists its rows in ascending order; a segment too
+//              long for the in-register sort sets unsorted[b] (s1 bytes, zero on entry)
 hipError_t launch_bucket_scatter(int64_t m, int64_t s1, int nchunk, const uint32_t* codes, const uint32_t* offsets, uint32_t* hist,
-                                 uint32_t* entries, hipStream_t s);
+                                 uint32_t* entries, uint8_t* unsorted, hipStream_t s);
+// True when launch_bucket_scatter leaves the buckets sorted (up to the flagged ones).
+bool bucket_scatter_sorts(int64_t s1);
 // W1[b, :] = sum over the bucket's rows (ascending row order) of sign * V[row, :]; the float
 // overload rounds each entry of V to FP32 and accumulates in FP32 (single-precision sketch).
+// unsorted == nullptr: every bucket is sorted here; otherwise only the flagged ones are.
 hipError_t launch_bucket_gather(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, const uint32_t* offsets,
-                                const uint32_t* entries, double* W1, hipStream_t s);
+                                const uint32_t* entries, const uint8_t* unsorted, double* W1, hipStream_t s);
 hipError_t launch_bucket_gather(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, const uint32_t* offsets,
-                                const uint32_t* entries, float* W1, hipStream_t s);
+                                const uint32_t* entries, const uint8_t* unsorted, float* W1, hipStream_t s);
 // Small-s1 CountSketch: per-wave LDS copies of W1; writes one partial W1 per workgroup.
 int countsketch_lds_parts(int64_t m, int64_t s1, int n);
 bool countsketch_lds_fits(int64_t s1, int n);
@@ -41,7 +48,8 @@ hipError_t launch_gauss_gemm(const double* W1, int n, int64_t s1, int64_t s2, ui
 // operands rounded to BF16 (bf16 = true); FP32 accumulation.
 hipError_t launch_gauss_mfma(const float* W1, int n, int64_t s1, int64_t s2, uint64_t seed, double scale, int64_t kc_len,
                              int64_t nkc, bool bf16, float* wpart, hipStream_t s);
-// out[i] = sum_{p = 0..nparts-1} parts[p * stride + i] in increasing p (compensated).
+// out[i] = sum_{p = 0..nparts-1} parts[p * stride + i], compensated, in a fixed order that depends
+// only on nparts (16 interleaved groups of parts, then the group sums in order).
 hipError_t launch_reduce_parts(const double* parts, int64_t nparts, int64_t stride, int64_t len, double* out,
                                hipStream_t s);
 hipError_t launch_reduce_parts(const float* parts, int64_t nparts, int64_t stride, int64_t len, float* out, hipStream_t s);

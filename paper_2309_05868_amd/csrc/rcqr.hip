@@ -29,7 +29,7 @@ int padded_cols(int64_t n) {
 }
 
 struct Layout {
-  size_t info, w1, csparts, codes, counts, offsets, hist, entries, wpart, w, qra, qrb, r0, r0pk, gpart, gc, g, r1, r1pk,
+  size_t info, w1, csparts, codes, counts, offsets, hist, entries, unsorted, wpart, w, qra, qrb, r0, r0pk, gpart, gc, g, r1, r1pk,
       ra, rapk, rtmp, rtmp2, total;
 };
 
@@ -93,6 +93,7 @@ Layout make_layout(const Shape& sh) {
   L.offsets = take(sh.lds_cs ? 0 : (ss + 1) * 4);
   L.hist = take(sh.lds_cs ? 0 : (size_t)sh.nchunk * ss * 4);
   L.entries = take(mm * 4);
+  L.unsorted = take(ss);
   L.wpart = take((size_t)sh.nkc * sh.s2 * n * 8);
   L.w = take((size_t)sh.s2 * n * 8);
   L.qra = take((size_t)sh.qr_blocks0 * n * n * 8);
@@ -220,10 +221,11 @@ static rcqr_status_t run_sketch(rcqr_plan_t p, const double* V, int64_t ldv) {
     uint32_t* codes = p->at<uint32_t>(L.codes);
     uint32_t* entries = p->at<uint32_t>(L.entries);
     RCQR_TRY(launch_hash_hist(sh.m, sh.s1, p->seed, sh.nchunk, codes, hist, s));
-    RCQR_TRY(launch_hist_colscan(sh.nchunk, sh.s1, hist, counts, s));
+    uint8_t* unsorted = p->at<uint8_t>(L.unsorted);
+    RCQR_TRY(launch_hist_colscan(sh.nchunk, sh.s1, hist, counts, unsorted, s));
     RCQR_TRY(launch_bucket_scan(counts, sh.s1, offsets, nullptr, s));
-    RCQR_TRY(launch_bucket_scatter(sh.m, sh.s1, sh.nchunk, codes, offsets, hist, entries, s));
-    RCQR_TRY(launch_bucket_gather(V, ldv, sh.m, n, sh.s1, offsets, entries, W1, s));
+    RCQR_TRY(launch_bucket_scatter(sh.m, sh.s1, sh.nchunk, codes, offsets, hist, entries, unsorted, s));
+    RCQR_TRY(launch_bucket_gather(V, ldv, sh.m, n, sh.s1, offsets, entries, bucket_scatter_sorts(sh.s1) ? unsorted : nullptr, W1, s));
   }
   if (mark(p, 1) != RCQR_OK) return RCQR_E_HIP;
   const double scale = 1.0 / std::sqrt((double)sh.s2);

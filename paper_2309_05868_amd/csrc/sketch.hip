@@ -96,8 +96,10 @@ hipError_t launch_hash_hist(int64_t m, int64_t s1, uint64_t seed, int nchunk, ui
 
 // hist[chunk][b] <- rows of bucket b in earlier chunks (exclusive scan down each column);
 // counts[b] <- total rows of bucket b.
-__global__ __launch_bounds__(256) void hist_colscan_kernel(int nchunk, int64_t s1, uint32_t* __restrict__ hist, uint32_t* __restrict__ counts) {
+__global__ __launch_bounds__(256) void hist_colscan_kernel(int nchunk, int64_t s1, uint32_t* __restrict__ hist, uint32_t* __restrict__ counts,
+                                                           uint8_t* __restrict__ unsorted) {
   for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < s1; b += (int64_t)gridDim.x * blockDim.x) {
+    if (unsorted) unsorted[b] = 0;
     // the loads of a batch are independent: issue them together, then scan and store
     constexpr int BATCH = 16;
     uint32_t run = 0;
@@ -115,8 +117,8 @@ __global__ __launch_bounds__(256) void hist_colscan_kernel(int nchunk, int64_t s
   }
 }
 
-hipError_t launch_hist_colscan(int nchunk, int64_t s1, uint32_t* hist, uint32_t* counts, hipStream_t s) {
-  hipLaunchKernelGGL(hist_colscan_kernel, dim3(grid_for(s1, 256, 2048)), dim3(256), 0, s, nchunk, s1, hist, counts);
+hipError_t launch_hist_colscan(int nchunk, int64_t s1, uint32_t* hist, uint32_t* counts, uint8_t* unsorted, hipStream_t s) {
+  hipLaunchKernelGGL(hist_colscan_kernel, dim3(grid_for(s1, 256, 2048)), dim3(256), 0, s, nchunk, s1, hist, counts, unsorted);
   return hipGetLastError();
 }
 
@@ -175,17 +177,56 @@ hipError_t launch_bucket_scan(const uint32_t* counts, int64_t s1, uint32_t* offs
   return hipGetLastError();
 }
 
+// Ascending sort of p[0..len) (len <= N, distinct keys) by a bitonic network in registers.
+template <int N>
+__device__ __forceinline__ void sort_segment(uint32_t* p, int len) {
+  uint32_t v[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = i < len ? p[i] : 0xFFFFFFFFu;
+#pragma unroll
+  for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int l = i ^ j;
+        if (l > i) {
+          const uint32_t a = v[i], b = v[l];
+          const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+          const bool up = (i & k) == 0;
+          v[i] = up ? lo : hi;
+          v[l] = up ? hi : lo;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    if (i < len) p[i] = v[i];
+}
+
+bool bucket_scatter_sorts(int64_t s1) { return s1 <= (int64_t)kHistLds; }
+
 // entries[offsets[b] + base(chunk, b) + k] = (row << 1) | signbit for the k-th row of the chunk
-// in bucket b (k from an LDS counter; the order inside a chunk is whatever the atomics give,
-// which the gather's sort removes).
+// in bucket b.  k comes from an LDS counter, so the order inside a chunk's segment is whatever
+// the atomics give; the segment (this workgroup's rows of bucket b, typically a few) is then
+// sorted in registers.  Segments follow each other in chunk order, so each bucket ends up in
+// ascending row order.  A segment longer than the largest network flags its bucket for the
+// gather's own sort.  With the counters in global memory (s1 above the LDS limit) the
+// segments are left as they are and the gather sorts every bucket.
 __global__ __launch_bounds__(256) void bucket_scatter_kernel(int64_t m, int64_t s1, int64_t chunk_rows, const uint32_t* __restrict__ codes,
                                                              const uint32_t* __restrict__ offsets, uint32_t* __restrict__ hist,
-                                                             uint32_t* __restrict__ entries) {
+                                                             uint32_t* entries, uint8_t* __restrict__ unsorted) {
   __shared__ uint32_t cur[kHistLds];
+  __shared__ uint32_t seg0[kHistLds];  // start of this chunk's segment of each bucket
   const bool in_lds = s1 <= (int64_t)kHistLds;
   uint32_t* gh = hist + (int64_t)blockIdx.x * s1;
   if (in_lds) {
-    for (int64_t b = threadIdx.x; b < s1; b += blockDim.x) cur[b] = offsets[b] + gh[b];
+    for (int64_t b = threadIdx.x; b < s1; b += blockDim.x) {
+      const uint32_t o = offsets[b] + gh[b];
+      cur[b] = o;
+      seg0[b] = o;
+    }
     __syncthreads();
   }
   const int64_t r_beg = (int64_t)blockIdx.x * chunk_rows;
@@ -196,13 +237,34 @@ __global__ __launch_bounds__(256) void bucket_scatter_kernel(int64_t m, int64_t 
     const uint32_t pos = in_lds ? atomicAdd(&cur[b], 1u) : offsets[b] + atomicAdd(&gh[b], 1u);
     entries[pos] = ((uint32_t)r << 1) | (code & 1u);
   }
+  if (!in_lds) return;
+  __syncthreads();  // the workgroup's entries are written and visible to the workgroup
+  for (int64_t b = threadIdx.x; b < s1; b += blockDim.x) {
+    const uint32_t beg = seg0[b];
+    const int len = (int)(cur[b] - beg);
+    if (len <= 1) continue;
+    uint32_t* seg = entries + beg;
+    if (len <= 4)
+      sort_segment<4>(seg, len);
+    else if (len <= 8)
+      sort_segment<8>(seg, len);
+    else if (len <= 16)
+      sort_segment<16>(seg, len);
+    else if (len <= 32)
+      sort_segment<32>(seg, len);
+    else if (len <= 64)
+      sort_segment<64>(seg, len);
+    else
+      unsorted[b] = 1;
+  }
 }
 
 hipError_t launch_bucket_scatter(int64_t m, int64_t s1, int nchunk, const uint32_t* codes, const uint32_t* offsets, uint32_t* hist,
-                                 uint32_t* entries, hipStream_t s) {
+                                 uint32_t* entries, uint8_t* unsorted, hipStream_t s) {
   if (m <= 0) return hipSuccess;
+  if (bucket_scatter_sorts(s1) && unsorted == nullptr) return hipErrorInvalidValue;
   hipLaunchKernelGGL(bucket_scatter_kernel, dim3(nchunk), dim3(256), 0, s, m, s1, bucket_chunk_rows(m, nchunk), codes, offsets, hist,
-                     entries);
+                     entries, unsorted);
   return hipGetLastError();
 }
 
@@ -290,7 +352,8 @@ __device__ __forceinline__ void gather_rows(const uint32_t* keys, int cnt, const
 template <int NPL, class T>
 __global__ __launch_bounds__(256) void bucket_gather_kernel(const double* __restrict__ V, int64_t ldv, int64_t m, int n, int64_t s1,
                                                             const uint32_t* __restrict__ offsets,
-                                                            const uint32_t* __restrict__ entries, T* __restrict__ W1) {
+                                                            const uint32_t* __restrict__ entries,
+                                                            const uint8_t* __restrict__ unsorted, T* __restrict__ W1) {
   __shared__ uint32_t keys_all[kGatherWaves][kSortCap];
   const int wave = threadIdx.x / kWave;
   const int lane = lane_id();
@@ -303,7 +366,17 @@ __global__ __launch_bounds__(256) void bucket_gather_kernel(const double* __rest
   acc[0] = T(0);
   if constexpr (NPL > 64) acc[1] = T(0);
 
-  if (L <= kSortCap) {
+  if (unsorted != nullptr && unsorted[b] == 0) {
+    // already in ascending row order: consecutive slices through LDS (one coalesced copy each,
+    // so the row addresses come from LDS), no sort
+    for (int64_t s0 = 0; s0 < L; s0 += kSortCap) {
+      const int cnt = (int)(L - s0 < kSortCap ? L - s0 : kSortCap);
+      for (int i = lane; i < cnt; i += kWave) keys[i] = entries[beg + s0 + i];
+      wave_lds_sync();
+      gather_rows<NPL, T>(keys, cnt, V, ldv, n, lane, acc);
+      wave_lds_sync();
+    }
+  } else if (L <= kSortCap) {
     int N = 1;
     while (N < L) N <<= 1;
     for (int i = lane; i < N; i += kWave) keys[i] = i < L ? entries[beg + i] : 0xFFFFFFFFu;
@@ -368,29 +441,29 @@ __global__ __launch_bounds__(256) void bucket_gather_kernel(const double* __rest
 
 template <class T>
 static hipError_t bucket_gather_any(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, const uint32_t* offsets,
-                                    const uint32_t* entries, T* W1, hipStream_t s) {
+                                    const uint32_t* entries, const uint8_t* unsorted, T* W1, hipStream_t s) {
   const dim3 grid((unsigned)((s1 + kGatherWaves - 1) / kGatherWaves)), block(256);
   if (n <= 8)
-    hipLaunchKernelGGL((bucket_gather_kernel<8, T>), grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, W1);
+    hipLaunchKernelGGL((bucket_gather_kernel<8, T>), grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, unsorted, W1);
   else if (n <= 16)
-    hipLaunchKernelGGL((bucket_gather_kernel<16, T>), grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, W1);
+    hipLaunchKernelGGL((bucket_gather_kernel<16, T>), grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, unsorted, W1);
   else if (n <= 32)
-    hipLaunchKernelGGL((bucket_gather_kernel<32, T>), grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, W1);
+    hipLaunchKernelGGL((bucket_gather_kernel<32, T>), grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, unsorted, W1);
   else if (n <= 64)
-    hipLaunchKernelGGL((bucket_gather_kernel<64, T>), grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, W1);
+    hipLaunchKernelGGL((bucket_gather_kernel<64, T>), grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, unsorted, W1);
   else
-    hipLaunchKernelGGL((bucket_gather_kernel<128, T>), grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, W1);
+    hipLaunchKernelGGL((bucket_gather_kernel<128, T>), grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, unsorted, W1);
   return hipGetLastError();
 }
 
 hipError_t launch_bucket_gather(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, const uint32_t* offsets,
-                                const uint32_t* entries, double* W1, hipStream_t s) {
-  return bucket_gather_any(V, ldv, m, n, s1, offsets, entries, W1, s);
+                                const uint32_t* entries, const uint8_t* unsorted, double* W1, hipStream_t s) {
+  return bucket_gather_any(V, ldv, m, n, s1, offsets, entries, unsorted, W1, s);
 }
 
 hipError_t launch_bucket_gather(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, const uint32_t* offsets,
-                                const uint32_t* entries, float* W1, hipStream_t s) {
-  return bucket_gather_any(V, ldv, m, n, s1, offsets, entries, W1, s);
+                                const uint32_t* entries, const uint8_t* unsorted, float* W1, hipStream_t s) {
+  return bucket_gather_any(V, ldv, m, n, s1, offsets, entries, unsorted, W1, s);
 }
 
 // ------------------------------------------------------------------------------------------
