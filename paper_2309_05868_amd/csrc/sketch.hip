@@ -95,30 +95,50 @@ hipError_t launch_hash_hist(int64_t m, int64_t s1, uint64_t seed, int nchunk, ui
 }
 
 // hist[chunk][b] <- rows of bucket b in earlier chunks (exclusive scan down each column);
-// counts[b] <- total rows of bucket b.
+// counts[b] <- total rows of bucket b.  Workgroup: 32 buckets x 8 chunk segments; each thread
+// scans its segment of one column, the segment totals are combined through LDS.
 __global__ __launch_bounds__(256) void hist_colscan_kernel(int nchunk, int64_t s1, uint32_t* __restrict__ hist, uint32_t* __restrict__ counts,
                                                            uint8_t* __restrict__ unsorted) {
-  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < s1; b += (int64_t)gridDim.x * blockDim.x) {
-    if (unsorted) unsorted[b] = 0;
-    // the loads of a batch are independent: issue them together, then scan and store
-    constexpr int BATCH = 16;
-    uint32_t run = 0;
-    for (int c0 = 0; c0 < nchunk; c0 += BATCH) {
-      uint32_t v[BATCH];
+  constexpr int NB = 32, NS = 8, BATCH = 8;
+  __shared__ uint32_t segtot[NS][NB];
+  const int bl = threadIdx.x % NB, sg = threadIdx.x / NB;
+  const int64_t b = (int64_t)blockIdx.x * NB + bl;
+  const int per = (nchunk + NS - 1) / NS;
+  const int c_beg = sg * per, c_end = c_beg + per < nchunk ? c_beg + per : nchunk;
+  uint32_t v[BATCH];
+  uint32_t run = 0;
+  // pass 1: segment total
+  if (b < s1) {
+    for (int c0 = c_beg; c0 < c_end; c0 += BATCH) {
 #pragma unroll
-      for (int u = 0; u < BATCH; ++u) v[u] = (c0 + u < nchunk) ? hist[(int64_t)(c0 + u) * s1 + b] : 0u;
+      for (int u = 0; u < BATCH; ++u) v[u] = (c0 + u < c_end) ? hist[(int64_t)(c0 + u) * s1 + b] : 0u;
 #pragma unroll
-      for (int u = 0; u < BATCH; ++u) {
-        if (c0 + u < nchunk) hist[(int64_t)(c0 + u) * s1 + b] = run;
-        run += v[u];
-      }
+      for (int u = 0; u < BATCH; ++u) run += v[u];
     }
-    counts[b] = run;
+  }
+  segtot[sg][bl] = run;
+  __syncthreads();
+  if (b >= s1) return;
+  uint32_t pre = 0;
+  for (int h = 0; h < sg; ++h) pre += segtot[h][bl];
+  if (sg == NS - 1) {
+    counts[b] = pre + run;
+    if (unsorted) unsorted[b] = 0;
+  }
+  // pass 2: exclusive prefix within the segment (the values are L2-resident from pass 1)
+  for (int c0 = c_beg; c0 < c_end; c0 += BATCH) {
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) v[u] = (c0 + u < c_end) ? hist[(int64_t)(c0 + u) * s1 + b] : 0u;
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) {
+      if (c0 + u < c_end) hist[(int64_t)(c0 + u) * s1 + b] = pre;
+      pre += v[u];
+    }
   }
 }
 
 hipError_t launch_hist_colscan(int nchunk, int64_t s1, uint32_t* hist, uint32_t* counts, uint8_t* unsorted, hipStream_t s) {
-  hipLaunchKernelGGL(hist_colscan_kernel, dim3(grid_for(s1, 256, 2048)), dim3(256), 0, s, nchunk, s1, hist, counts, unsorted);
+  hipLaunchKernelGGL(hist_colscan_kernel, dim3((unsigned)((s1 + 31) / 32)), dim3(256), 0, s, nchunk, s1, hist, counts, unsorted);
   return hipGetLastError();
 }
 
@@ -143,33 +163,48 @@ hipError_t launch_hash_debug(int64_t row0, int64_t count, int64_t s1, uint64_t s
 // ------------------------------------------------------------------------------------------
 // Bucket index: exclusive scan (one workgroup) and scatter.
 // ------------------------------------------------------------------------------------------
+// Tiles of 8192 counts: each thread scans 8 consecutive counts, the 1024 thread totals are
+// scanned by waves (shuffles) and across the 16 waves through LDS, plus the carry of earlier tiles.
 __global__ __launch_bounds__(1024) void bucket_scan_kernel(const uint32_t* __restrict__ counts, int64_t s1,
                                                            uint32_t* __restrict__ offsets, uint32_t* __restrict__ cursor) {
-  __shared__ uint32_t part[1024];
-  __shared__ uint32_t carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int64_t base = 0; base < s1; base += 1024) {
-    const int64_t i = base + threadIdx.x;
-    const uint32_t v = i < s1 ? counts[i] : 0u;
-    part[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {  // Hillis-Steele inclusive scan
-      const uint32_t add = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
-      __syncthreads();
-      part[threadIdx.x] += add;
-      __syncthreads();
+  constexpr int PER = 8;
+  __shared__ uint32_t wsum[16];
+  __shared__ uint32_t carry_s;
+  const int t = threadIdx.x, lane = lane_id(), wave = t / kWave;
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < s1; base += 1024 * PER) {
+    const int64_t i0 = base + (int64_t)t * PER;
+    uint32_t v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) v[u] = i0 + u < s1 ? counts[i0 + u] : 0u;
+    uint32_t tot = 0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) tot += v[u];
+    // inclusive scan of the thread totals within the wave
+    uint32_t inc = tot;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t y = __shfl_up(inc, off, kWave);
+      if (lane >= off) inc += y;
     }
-    const uint32_t incl = part[threadIdx.x] + carry;
-    if (i < s1) {
-      offsets[i] = incl - v;
-      if (cursor) cursor[i] = incl - v;
+    if (lane == kWave - 1) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t before = carry;
+    for (int w = 0; w < wave; ++w) before += wsum[w];
+    uint32_t run = before + inc - tot;  // exclusive prefix of this thread's first count
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      if (i0 + u < s1) {
+        offsets[i0 + u] = run;
+        if (cursor) cursor[i0 + u] = run;
+      }
+      run += v[u];
     }
+    if (t == 1023) carry_s = run;
     __syncthreads();
-    if (threadIdx.x == 1023) carry = incl;
-    __syncthreads();
+    carry = carry_s;
   }
-  if (threadIdx.x == 0) offsets[s1] = carry;
+  if (t == 0) offsets[s1] = carry;
 }
 
 hipError_t launch_bucket_scan(const uint32_t* counts, int64_t s1, uint32_t* offsets, uint32_t* cursor, hipStream_t s) {
