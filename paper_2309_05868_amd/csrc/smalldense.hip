@@ -23,7 +23,10 @@ namespace rcqr {
 // l + 128, l + 192, so every column reduction is one wave's butterfly.  Reflector j is built by
 // the owner of column j: it maps x = A[j:, j] to beta e1, beta = -sign(x0) ||x||,
 // H = I - tau v v^T with v[0] = 1; v and tau go through LDS (double-buffered, so one workgroup
-// barrier per reflector) and every wave applies H to its columns right of j.
+// barrier per reflector) and every wave applies H to its columns right of j.  Look-ahead: the
+// owner of column j + 1 applies H_j to that column first and publishes reflector j + 1 before
+// updating its other columns, at raised wave priority, so the serial chain per reflector is one
+// column update, one norm and the reflector (the order of every column's operations is unchanged).
 // ------------------------------------------------------------------------------------------
 constexpr int kQrMaxRows = 256;
 constexpr int kQrWaves = 16;
@@ -50,77 +53,91 @@ __global__ __launch_bounds__(kQrWaves * kWave) void qr_block_kernel(const T* __r
       a[q][e] = (r < p && c < n) ? A0[(int64_t)r * ldin + c] : T(0);
     }
   }
-  const int steps = n < p ? n : p;
-  for (int j = 0; j < steps; ++j) {
-    const int buf = j & 1;
-    if (wave == (j % kQrWaves)) {
-      const int oq = j / kQrWaves;
-      T x[ER];
+  // Reflector j from the owner's (fully updated) column j, into buffer j & 1.
+  auto make_reflector = [&](int j) {
+    const int oq = j / kQrWaves, buf = j & 1;
+    T x[ER];
 #pragma unroll
-      for (int e = 0; e < ER; ++e) x[e] = T(0);
+    for (int e = 0; e < ER; ++e) x[e] = T(0);
 #pragma unroll
-      for (int q = 0; q < NC; ++q)
-        if (q == oq) {
+    for (int q = 0; q < NC; ++q)
+      if (q == oq) {
 #pragma unroll
-          for (int e = 0; e < ER; ++e) x[e] = a[q][e];
-        }
-      T ss = T(0);
-#pragma unroll
-      for (int e = 0; e < ER; ++e) {
-        const int r = lane + kWave * e;
-        if (r > j) ss = fma_t(x[e], x[e], ss);
+        for (int e = 0; e < ER; ++e) x[e] = a[q][e];
       }
-      ss = wave_reduce_sum(ss);
-      T xsel = T(0);
+    T ss = T(0);
 #pragma unroll
-      for (int e = 0; e < ER; ++e) xsel = (e == (j / kWave)) ? x[e] : xsel;
-      const T alpha = readlane_d(xsel, j % kWave);
-      T tau = T(0), beta = alpha, scal = T(0);
-      if (ss != T(0)) {
-        beta = -copysign(sqrt(fma_t(alpha, alpha, ss)), alpha);
-        tau = (beta - alpha) / beta;
-        scal = T(1) / (alpha - beta);
-      }
-#pragma unroll
-      for (int e = 0; e < ER; ++e) {
-        const int r = lane + kWave * e;
-        vbuf[buf][r] = (r == j) ? T(1) : (r > j ? x[e] * scal : T(0));
-        x[e] = (r == j) ? beta : (r > j ? T(0) : x[e]);
-      }
-#pragma unroll
-      for (int q = 0; q < NC; ++q)
-        if (q == oq) {
-#pragma unroll
-          for (int e = 0; e < ER; ++e) a[q][e] = x[e];
-        }
-      if (lane == 0) taub[buf] = tau;
+    for (int e = 0; e < ER; ++e) {
+      const int r = lane + kWave * e;
+      if (r > j) ss = fma_t(x[e], x[e], ss);
     }
-    __syncthreads();
-    const T tau = taub[buf];
-    if (tau != T(0)) {
-      T v[ER];
+    ss = wave_reduce_sum(ss);
+    T xsel = T(0);
 #pragma unroll
-      for (int e = 0; e < ER; ++e) v[e] = vbuf[buf][lane + kWave * e];
-      T d[NC];
+    for (int e = 0; e < ER; ++e) xsel = (e == (j / kWave)) ? x[e] : xsel;
+    const T alpha = readlane_d(xsel, j % kWave);
+    T tau = T(0), beta = alpha, scal = T(0);
+    if (ss != T(0)) {
+      beta = -copysign(sqrt(fma_t(alpha, alpha, ss)), alpha);
+      tau = (beta - alpha) / beta;
+      scal = T(1) / (alpha - beta);
+    }
 #pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        d[q] = T(0);
-        const int c = wave + kQrWaves * q;
-        if (c > j && c < n) {
+    for (int e = 0; e < ER; ++e) {
+      const int r = lane + kWave * e;
+      vbuf[buf][r] = (r == j) ? T(1) : (r > j ? x[e] * scal : T(0));
+      x[e] = (r == j) ? beta : (r > j ? T(0) : x[e]);
+    }
 #pragma unroll
-          for (int e = 0; e < ER; ++e) d[q] = fma_t(v[e], a[q][e], d[q]);
-          d[q] = wave_reduce_sum(d[q]);
-        }
+    for (int q = 0; q < NC; ++q)
+      if (q == oq) {
+#pragma unroll
+        for (int e = 0; e < ER; ++e) a[q][e] = x[e];
       }
+    if (lane == 0) taub[buf] = tau;
+  };
+  // H_j applied to the wave's column q (when it lies right of j): a -= tau (v . a) v
+  auto apply = [&](int q, int j, T tau, const T (&v)[ER]) {
+    const int c = wave + kQrWaves * q;
+    if (c > j && c < n) {
+      T d = T(0);
 #pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        const int c = wave + kQrWaves * q;
-        if (c > j && c < n) {
-          const T tw = tau * d[q];
+      for (int e = 0; e < ER; ++e) d = fma_t(v[e], a[q][e], d);
+      d = wave_reduce_sum(d);
+      const T tw = tau * d;
 #pragma unroll
-          for (int e = 0; e < ER; ++e) a[q][e] = fma_t(-tw, v[e], a[q][e]);
-        }
+      for (int e = 0; e < ER; ++e) a[q][e] = fma_t(-tw, v[e], a[q][e]);
+    }
+  };
+  const int steps = n < p ? n : p;
+  if (steps > 0 && wave == 0) make_reflector(0);
+  for (int j = 0; j < steps; ++j) {
+    __syncthreads();  // reflector j published; every read of reflector j - 1 is done
+    const T tau = taub[j & 1];
+    T v[ER];
+#pragma unroll
+    for (int e = 0; e < ER; ++e) v[e] = vbuf[j & 1][lane + kWave * e];
+    const int nxt = j + 1;
+    if (nxt < steps && wave == nxt % kQrWaves) {
+      // look-ahead: this wave owns column j + 1, the only work on the path to the next
+      // barrier; it runs at raised priority, its other columns afterwards
+      const int nq = nxt / kQrWaves;
+      __builtin_amdgcn_s_setprio(3);
+      if (tau != T(0)) {
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+          if (q == nq) apply(q, j, tau, v);
       }
+      make_reflector(nxt);
+      __builtin_amdgcn_s_setprio(0);
+      if (tau != T(0)) {
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+          if (q != nq) apply(q, j, tau, v);
+      }
+    } else if (tau != T(0)) {
+#pragma unroll
+      for (int q = 0; q < NC; ++q) apply(q, j, tau, v);
     }
   }
   T* R = out + (int64_t)blockIdx.x * n * n;
@@ -257,7 +274,9 @@ __device__ __forceinline__ int upper_block_index(int a, int b, int nb) {
 // inside it on its own (pivots and coupling coefficients read from the owning lanes; no workgroup
 // barrier), writes the four rows G[4J + r][.] and 1/pivot to LDS and, after one barrier, every
 // thread applies the rank-4 update G[i][c] -= sum_r (G[4J+r][i] / d_r) G[4J+r][c] to its rows
-// below the block (j < i <= c, branch-free).  A pivot that is not > 0 (NaN included) stops every
+// below the block (j < i <= c, branch-free).  Look-ahead: the owner of block J + 1 updates that
+// block first and publishes it, at raised wave priority, before its other rows (the operations
+// on every row are unchanged, only their order across rows).  A pivot that is not > 0 (NaN included) stops every
 // thread at the same step.  R1[j][j] = sqrt(d_j), R1[j][c] = G[j][c] / sqrt(d_j) are formed at
 // the end for all rows at once.
 template <int NP>
@@ -276,7 +295,8 @@ __global__ __launch_bounds__(CholShape<NP>::NWV * kWave) void cholesky_kernel(co
                                                                               double* __restrict__ r_out, int64_t ldr) {
   constexpr int NWV = CholShape<NP>::NWV, CPL = CholShape<NP>::CPL, BR = CholShape<NP>::BR, NBT = CholShape<NP>::NBT;
   constexpr int NB = NP / 16;
-  extern __shared__ double Rl[];  // NP x NP, the rows of the LDL^T elimination
+  extern __shared__ double Rl[];  // NP x NP, the rows of the LDL^T elimination; then Rprev (NP <= 64)
+  double* rp = Rl + NP * NP;
   __shared__ double sdiag[NP];
   __shared__ double dinvb[2][BR];
   __shared__ int failb[2];
@@ -317,53 +337,76 @@ __global__ __launch_bounds__(CholShape<NP>::NWV * kWave) void cholesky_kernel(co
   }
   int bad = 0;
   const int nblk = (n + BR - 1) / BR;
-  for (int J = 0; J < nblk; ++J) {
+  // In-block elimination of row block J by its owner (rows already updated by every earlier
+  // block): pivots and coupling coefficients from the owning lanes, rows to LDS.
+  auto eliminate = [&](int J) {
     const int buf = J & 1;
     const int j0 = BR * J;
-    if (w == J % NWV) {
-      const int kJ = J / NWV;
-      double rows[BR][CPL];
+    const int kJ = J / NWV;
+    double rows[BR][CPL];
 #pragma unroll
-      for (int r = 0; r < BR; ++r)
+    for (int r = 0; r < BR; ++r)
 #pragma unroll
-        for (int q = 0; q < CPL; ++q) {
-          double v = 0.0;
+      for (int q = 0; q < CPL; ++q) {
+        double v = 0.0;
 #pragma unroll
-          for (int kb = 0; kb < NBT; ++kb) v = (kb == kJ) ? g[kb][r][q] : v;
-          rows[r][q] = v;
-        }
-      // column j0 + r lives in lane (j0 + r) % 64 of part (j0 + r) / 64 (the same part for the block)
-      const int qj = (CPL > 1 && j0 >= kWave) ? 1 : 0;
-      int fail = 0;
-#pragma unroll
-      for (int r = 0; r < BR; ++r) {
-        const int j = j0 + r;
-        const double d = readlane_d(qj ? rows[r][CPL - 1] : rows[r][0], j % kWave);
-        const bool live = j < n;
-        if (live && !(d > 0.0) && fail == 0) fail = j + 1;
-        const double dinv = 1.0 / d;
-        if (l == 0) dinvb[buf][r] = live ? dinv : 0.0;
-#pragma unroll
-        for (int r2 = r + 1; r2 < BR; ++r2) {
-          const double coef = readlane_d(qj ? rows[r][CPL - 1] : rows[r][0], (j0 + r2) % kWave) * dinv;
-#pragma unroll
-          for (int q = 0; q < CPL; ++q) {
-            const int c = l + kWave * q;
-            const double upd = __builtin_fma(-coef, rows[r][q], rows[r2][q]);
-            rows[r2][q] = (live && c >= j0 + r2) ? upd : rows[r2][q];
-          }
-        }
+        for (int kb = 0; kb < NBT; ++kb) v = (kb == kJ) ? g[kb][r][q] : v;
+        rows[r][q] = v;
       }
+    // column j0 + r lives in lane (j0 + r) % 64 of part (j0 + r) / 64 (the same part for the block)
+    const int qj = (CPL > 1 && j0 >= kWave) ? 1 : 0;
+    int fail = 0;
 #pragma unroll
-      for (int r = 0; r < BR; ++r)
+    for (int r = 0; r < BR; ++r) {
+      const int j = j0 + r;
+      const double d = readlane_d(qj ? rows[r][CPL - 1] : rows[r][0], j % kWave);
+      const bool live = j < n;
+      if (live && !(d > 0.0) && fail == 0) fail = j + 1;
+      const double dinv = 1.0 / d;
+      if (l == 0) dinvb[buf][r] = live ? dinv : 0.0;
+#pragma unroll
+      for (int r2 = r + 1; r2 < BR; ++r2) {
+        const double coef = readlane_d(qj ? rows[r][CPL - 1] : rows[r][0], (j0 + r2) % kWave) * dinv;
 #pragma unroll
         for (int q = 0; q < CPL; ++q) {
           const int c = l + kWave * q;
-          if (c < NP && j0 + r < NP) Rl[(j0 + r) * NP + c] = (c >= j0 + r) ? rows[r][q] : 0.0;
+          const double upd = __builtin_fma(-coef, rows[r][q], rows[r2][q]);
+          rows[r2][q] = (live && c >= j0 + r2) ? upd : rows[r2][q];
         }
-      if (l == 0) failb[buf] = fail;
+      }
     }
-    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < BR; ++r)
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) {
+        const int c = l + kWave * q;
+        if (c < NP && j0 + r < NP) Rl[(j0 + r) * NP + c] = (c >= j0 + r) ? rows[r][q] : 0.0;
+      }
+    if (l == 0) failb[buf] = fail;
+  };
+  // Rank-BR update of the thread's row block kb by row block J (rows below the block only).
+  auto update = [&](int kb, int j0, const double (&gj)[BR][CPL], const double (&di)[BR]) {
+#pragma unroll
+    for (int r2 = 0; r2 < BR; ++r2) {
+      const int i = BR * (w + NWV * kb) + r2;
+      double lij[BR];
+#pragma unroll
+      for (int r = 0; r < BR; ++r) lij[r] = Rl[(j0 + r) * NP + i] * di[r];
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) {
+        const int c = l + kWave * q;
+        double upd = g[kb][r2][q];
+#pragma unroll
+        for (int r = 0; r < BR; ++r) upd = __builtin_fma(-lij[r], gj[r][q], upd);
+        g[kb][r2][q] = (i >= j0 + BR && i <= c) ? upd : g[kb][r2][q];
+      }
+    }
+  };
+  if (nblk > 0 && w == 0) eliminate(0);
+  for (int J = 0; J < nblk; ++J) {
+    const int buf = J & 1;
+    const int j0 = BR * J;
+    __syncthreads();  // block J published; every read of block J - 1 is done
     const int f = failb[buf];
     if (f) {  // every thread read the same flag
       bad = f;
@@ -379,23 +422,24 @@ __global__ __launch_bounds__(CholShape<NP>::NWV * kWave) void cholesky_kernel(co
         gj[r][q] = (c < NP) ? Rl[(j0 + r) * NP + (c < NP ? c : 0)] : 0.0;
       }
     }
+    const int nx = J + 1;
+    if (nx < nblk && w == nx % NWV) {
+      // look-ahead: the owner of block J + 1 brings that block up to date and publishes it first
+      // (the only work on the path to the next barrier), at raised priority
+      const int nkb = nx / NWV;
+      __builtin_amdgcn_s_setprio(3);
 #pragma unroll
-    for (int kb = 0; kb < NBT; ++kb)
+      for (int kb = 0; kb < NBT; ++kb)
+        if (kb == nkb) update(kb, j0, gj, di);
+      eliminate(nx);
+      __builtin_amdgcn_s_setprio(0);
 #pragma unroll
-      for (int r2 = 0; r2 < BR; ++r2) {
-        const int i = BR * (w + NWV * kb) + r2;
-        double lij[BR];
+      for (int kb = 0; kb < NBT; ++kb)
+        if (kb != nkb) update(kb, j0, gj, di);
+    } else {
 #pragma unroll
-        for (int r = 0; r < BR; ++r) lij[r] = Rl[(j0 + r) * NP + i] * di[r];
-#pragma unroll
-        for (int q = 0; q < CPL; ++q) {
-          const int c = l + kWave * q;
-          double upd = g[kb][r2][q];
-#pragma unroll
-          for (int r = 0; r < BR; ++r) upd = __builtin_fma(-lij[r], gj[r][q], upd);
-          g[kb][r2][q] = (i >= j0 + BR && i <= c) ? upd : g[kb][r2][q];
-        }
-      }
+      for (int kb = 0; kb < NBT; ++kb) update(kb, j0, gj, di);
+    }
   }
   if (bad) {
     if (t == 0) {
@@ -421,6 +465,12 @@ __global__ __launch_bounds__(CholShape<NP>::NWV * kWave) void cholesky_kernel(co
     if (r < n && c < n) r1[r * n + c] = v;
     if (c >= r) put_packed(r1pk, NP, n, r, c, v);
   }
+  if constexpr (NP <= 64) {
+    // Rprev staged in LDS (one coalesced read), then the same sums in the same order
+    for (int idx = t; idx < n * n; idx += blockDim.x) rp[idx] = rprev[idx];
+    __syncthreads();
+  }
+  const double* rpv = NP <= 64 ? rp : rprev;
   for (int idx = t; idx < n * n; idx += blockDim.x) {
     const int r = idx / n, k = idx % n;
     double acc = 0.0;
@@ -429,21 +479,28 @@ __global__ __launch_bounds__(CholShape<NP>::NWV * kWave) void cholesky_kernel(co
       for (; m + 8 <= k + 1; m += 8) {  // eight independent loads in flight
         double pv[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) pv[u] = rprev[(m + u) * n + k];
+        for (int u = 0; u < 8; ++u) pv[u] = rpv[(m + u) * n + k];
 #pragma unroll
         for (int u = 0; u < 8; ++u) acc = __builtin_fma(Rl[r * NP + m + u], pv[u], acc);
       }
-      for (; m <= k; ++m) acc = __builtin_fma(Rl[r * NP + m], rprev[m * n + k], acc);
+      for (; m <= k; ++m) acc = __builtin_fma(Rl[r * NP + m], rpv[m * n + k], acc);
     }
     r_out[(int64_t)r * ldr + k] = acc;
   }
 }
 
+// Dynamic LDS: the NP x NP rows of the elimination, and up to 64 padded columns a second NP x NP
+// area that stages Rprev for the final product.
+template <int NP>
+constexpr size_t cholesky_lds() {
+  return (size_t)NP * NP * sizeof(double) * (NP <= 64 ? 2 : 1);
+}
+
 template <int NP>
 static hipError_t cholesky_prepare() {
-  constexpr size_t lds = (size_t)NP * NP * sizeof(double);
-  if constexpr (lds > 64 * 1024) {
-    static bool attr_set = false;  // 128 x 128 needs 128 KiB of dynamic LDS
+  constexpr size_t lds = cholesky_lds<NP>();
+  if constexpr (lds > 32 * 1024) {
+    static bool attr_set = false;  // 64 KiB (64 columns) and 128 KiB (128 columns) of dynamic LDS
     if (!attr_set) {
       const hipError_t e = hipFuncSetAttribute((const void*)cholesky_kernel<NP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
@@ -453,14 +510,16 @@ static hipError_t cholesky_prepare() {
   return hipSuccess;
 }
 
-hipError_t prepare_cholesky(int np) { return np == 128 ? cholesky_prepare<128>() : hipSuccess; }
+hipError_t prepare_cholesky(int np) {
+  return np == 128 ? cholesky_prepare<128>() : np == 64 ? cholesky_prepare<64>() : hipSuccess;
+}
 
 template <int NP>
 static hipError_t cholesky_any(const double* gcompact, int n, const double* rprev, double shift_coef, int32_t* info, double* g_out,
                                double* r1, double* r1pk, double* r_out, int64_t ldr, hipStream_t s) {
   const hipError_t e = cholesky_prepare<NP>();
   if (e != hipSuccess) return e;
-  const size_t lds = (size_t)NP * NP * sizeof(double);
+  const size_t lds = cholesky_lds<NP>();
   hipLaunchKernelGGL(cholesky_kernel<NP>, dim3(1), dim3(CholShape<NP>::NWV * kWave), lds, s, gcompact, n, rprev, shift_coef, info,
                      g_out, r1, r1pk, r_out, ldr);
   return hipGetLastError();
