@@ -393,6 +393,74 @@ def latency_workload(args):
     print(json.dumps(line), flush=True)
 
 
+BATCH_WORKLOAD = dict(count=64, m=10_000, n=16, kappa=1e4, s1=512, s2=64, seed=70)
+
+
+def batch_workload(args):
+    """Many small factorizations (the small configuration's shape, one V each), three ways:
+    eager calls one after another on one stream; eager calls on one stream per matrix (the host
+    launches about fifteen kernels per matrix); rcqr_batch (one captured graph per matrix,
+    launched concurrently on the matrices' streams).  QR/s over the whole batch; every batch
+    member is checked bitwise against its eager result."""
+    import torch
+
+    import paper_2309_05868_amd as rc
+    import synth
+
+    wl = BATCH_WORKLOAD
+    dev = torch.device("cuda:0")
+    k, m, n = wl["count"], wl["m"], wl["n"]
+    plans, Vs = [], []
+    for i in range(k):
+        st = torch.cuda.Stream(dev)
+        plans.append(rc.Plan(m, n, wl["s1"], wl["s2"], wl["seed"] + i, device=dev, stream=st))
+        Vs.append(torch.from_numpy(synth.make_V(m, n, wl["kappa"], wl["seed"] + i)).to(dev))
+    s_one = torch.cuda.Stream(dev)
+    one = [rc.Plan(m, n, wl["s1"], wl["s2"], wl["seed"] + i, device=dev, stream=s_one) for i in range(k)]
+    torch.cuda.synchronize()
+    batch = rc.Batch(plans, Vs)
+    Qe = [torch.empty_like(V) for V in Vs]
+    Re = [torch.empty((n, n), dtype=torch.float64, device=dev) for _ in Vs]
+    runs = {
+        "eager_one_stream": lambda: [p.factor(V, Q, R, check=False) for p, V, Q, R in zip(one, Vs, Qe, Re)],
+        "eager_stream_per_matrix": lambda: [p.factor(V, Q, R, check=False) for p, V, Q, R in zip(plans, Vs, Qe, Re)],
+        "batch": batch.launch,
+    }
+    reps = max(args.steps, 10)
+    res = {}
+    for name, call in runs.items():
+        for _ in range(args.warmup + 2):
+            call()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            call()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        res[name] = {"ms_per_batch": round(1e3 * dt, 4), "qr_per_s": round(k / dt, 1)}
+        print(f"bench: batch of {k} x ({m} x {n}), {name}: {1e3 * dt:.3f} ms per batch, {k / dt:.0f} QR/s", file=sys.stderr,
+              flush=True)
+    # the last eager run (one stream per matrix) used the same plans as the batch
+    for p, V, Q, R in zip(plans, Vs, Qe, Re):
+        p.factor(V, Q, R, check=False)
+    batch.launch()
+    torch.cuda.synchronize()
+    same = all(torch.equal(Qb, Q) and torch.equal(Rb, R) for Qb, Rb, Q, R in zip(batch.Qs, batch.Rs, Qe, Re))
+    st = [p.info()[0] for p in plans]
+    eye = torch.eye(n, dtype=torch.float64, device=dev)
+    orth = max(torch.linalg.norm(eye - gram_accurate(Q)).item() for Q in batch.Qs)
+    line = {"metric": METRIC, "value": res["batch"]["qr_per_s"], "unit": "QR/s", "n_gpus": 1, "steps": reps,
+            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": f"rand_cholQR batch of {k} matrices {m} x {n}, kappa {wl['kappa']:.0e}, s1 {wl['s1']}, s2 {wl['s2']}"},
+            "runs": res, "bitwise_equal_to_eager": same, "statuses_ok": all(x == 0 for x in st), "max_orth_error": orth,
+            "within_target": bool(orth <= 10 * n * U_PAPER)}
+    batch.close()
+    for p in plans + one:
+        p.close()
+    print(json.dumps(line), flush=True)
+
+
 def cpu_baseline(wl, sample_rows):
     """The oracle as it stands, single-threaded, on a row-scaled sample of the workload."""
     from threadpoolctl import threadpool_limits
@@ -425,7 +493,7 @@ def main():
     ap.add_argument("--tune", action="store_true", help="run rcqr_tune (result-neutral launch choices) before warm-up")
     ap.add_argument("--comparator-steps", type=int, default=5)
     ap.add_argument("--cpu-sample-rows", type=int, default=100_000)
-    ap.add_argument("--workload", choices=["default", "mixed", "serve", "latency", "sweep"], default="default",
+    ap.add_argument("--workload", choices=["default", "mixed", "serve", "latency", "sweep", "batch"], default="default",
                     help="mixed: FP32/BF16 preconditioner variants against FP64 at m=4e6, n=128, kappa=1e14; "
                          "serve: continuous batching of 4096 Poisson-arriving requests; "
                          "latency: small factorizations, eager vs HIP graph; sweep: n in {8, 32, 128} at 1-2 GB")
@@ -469,6 +537,9 @@ def main():
         return
     if args.workload == "sweep":
         sweep_workload(args)
+        return
+    if args.workload == "batch":
+        batch_workload(args)
         return
     wl = WORKLOAD
     m, n = wl["m"], wl["n"]

@@ -198,6 +198,32 @@ rcqr_status_t rcqr_graph_create(rcqr_plan_t plan, int32_t method, const double* 
 rcqr_status_t rcqr_graph_launch(rcqr_graph_t graph);
 rcqr_status_t rcqr_graph_destroy(rcqr_graph_t graph);
 
+/*
+ * Batches of factorizations.  rcqr_batch_create() records `count` factorizations, each on its own
+ * plan (any m, n, s1, s2, seed and flags) with its own V, Q and R (arrays of `count` entries):
+ * each is captured as a HIP graph on its plan's stream.  rcqr_batch_launch() launches every
+ * member's graph on its own stream, forked from the first plan's stream and joined back to it
+ * with events, so the members run concurrently: one factorization's single-workgroup steps (the
+ * Householder QR of the sketch, the Cholesky) overlap with the others' work, and the host issues
+ * one graph launch per member instead of about fifteen kernel launches.  The batch is complete
+ * when the first plan's stream reaches the launch.  (One graph holding every member as a
+ * parallel branch was measured to run its branches one after another on this ROCm, hence one
+ * graph per member.)  Requirements as for rcqr_graph_create on every plan (a non-default stream
+ * each; distinct streams run concurrently, plans sharing a stream run one after the other).  A
+ * plan may appear only once.  Each member gives bitwise the Q and R of an eager call on its plan;
+ * its status is read with rcqr_info() on its plan.  Plans, workspaces and matrices must stay
+ * valid while the batch exists; destroy the batch before the plans.
+ * Errors: RCQR_E_INVALID (count < 1, a null pointer or array, a plan on the default stream, a
+ * repeated plan, an invalid V/Q/R), RCQR_E_HIP (capture, instantiation or launch failed),
+ * RCQR_E_NOMEM.
+ */
+typedef struct rcqr_batch_s* rcqr_batch_t;
+rcqr_status_t rcqr_batch_create(int32_t count, const rcqr_plan_t* plans, int32_t method, const double* const* d_V,
+                                const int64_t* ldv, double* const* d_Q, const int64_t* ldq, double* const* d_R,
+                                const int64_t* ldr, rcqr_batch_t* batch);
+rcqr_status_t rcqr_batch_launch(rcqr_batch_t batch);
+rcqr_status_t rcqr_batch_destroy(rcqr_batch_t batch);
+
 /* ------------------------------------------------------------------------------------------
  * Inspection entry points (same library; used by tests, never on a timed path).
  * ------------------------------------------------------------------------------------------ */

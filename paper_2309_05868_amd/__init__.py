@@ -51,6 +51,11 @@ _SIGNATURES = {
     "rcqr_graph_create": (_c_i32, [_c_p, _c_i32, _c_p, _c_i64, _c_p, _c_i64, _c_p, _c_i64, ctypes.POINTER(_c_p)]),
     "rcqr_graph_launch": (_c_i32, [_c_p]),
     "rcqr_graph_destroy": (_c_i32, [_c_p]),
+    "rcqr_batch_create": (_c_i32, [_c_i32, ctypes.POINTER(_c_p), _c_i32, ctypes.POINTER(_c_p), ctypes.POINTER(_c_i64),
+                                   ctypes.POINTER(_c_p), ctypes.POINTER(_c_i64), ctypes.POINTER(_c_p), ctypes.POINTER(_c_i64),
+                                   ctypes.POINTER(_c_p)]),
+    "rcqr_batch_launch": (_c_i32, [_c_p]),
+    "rcqr_batch_destroy": (_c_i32, [_c_p]),
 }
 
 
@@ -274,6 +279,45 @@ class Graph:
     def close(self):
         if getattr(self, "_h", None):
             lib().rcqr_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several factorizations launched together (rcqr_batch_*): each member captured as a HIP
+    graph on its plan's stream, all launched concurrently, forked from and joined to plans[0]'s
+    stream.  plans[i] factors Vs[i] into Qs[i], Rs[i]; each plan needs its own non-default
+    stream."""
+
+    def __init__(self, plans, Vs, Qs=None, Rs=None, method="rand_cholqr"):
+        k = len(plans)
+        if k < 1 or len(Vs) != k:
+            raise ValueError("need one V per plan")
+        Qs = list(Qs) if Qs is not None else [None] * k
+        Rs = list(Rs) if Rs is not None else [None] * k
+        outs = [p._outputs(V, Q, R) for p, V, Q, R in zip(plans, Vs, Qs, Rs)]
+        self.plans, self.Vs = list(plans), list(Vs)
+        self.Qs, self.Rs = [o[0] for o in outs], [o[1] for o in outs]
+        P = (_c_p * k)(*[p._h for p in plans])
+        ptr = lambda ts: (_c_p * k)(*[t.data_ptr() for t in ts])  # noqa: E731
+        ld = lambda ts: (_c_i64 * k)(*[t.stride(0) for t in ts])  # noqa: E731
+        h = ctypes.c_void_p()
+        _check(lib().rcqr_batch_create(k, P, METHODS[method], ptr(self.Vs), ld(self.Vs), ptr(self.Qs), ld(self.Qs),
+                                       ptr(self.Rs), ld(self.Rs), ctypes.byref(h)), "rcqr_batch_create")
+        self._h = h
+
+    def launch(self):
+        _check(lib().rcqr_batch_launch(self._h), "rcqr_batch_launch")
+        return self.Qs, self.Rs
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rcqr_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -658,6 +658,122 @@ rcqr_status_t rcqr_graph_destroy(rcqr_graph_t g) {
   return RCQR_OK;
 }
 
+struct rcqr_batch_s {
+  int32_t count;
+  hipStream_t s0;              // the first plan's stream: fork and join point
+  hipStream_t* streams;        // each member's plan stream
+  hipGraph_t* graphs;          // one captured factorization per member
+  hipGraphExec_t* execs;
+  hipEvent_t fork;
+  hipEvent_t* join;            // per member (unused for members on s0)
+};
+
+static rcqr_status_t run_method(rcqr_plan_t p, int32_t method, const double* V, int64_t ldv, double* Q, int64_t ldq, double* R,
+                                int64_t ldr) {
+  if (method == RCQR_METHOD_RAND_CHOLQR) return rcqr_factor(p, V, ldv, Q, ldq, R, ldr);
+  if (method == RCQR_METHOD_CHOLQR2) return rcqr_cholqr2(p, V, ldv, Q, ldq, R, ldr);
+  return rcqr_scholqr3(p, V, ldv, Q, ldq, R, ldr);
+}
+
+static void free_batch(rcqr_batch_s* b) {
+  if (b == nullptr) return;
+  for (int32_t i = 0; i < b->count; ++i) {
+    if (b->execs && b->execs[i]) (void)hipGraphExecDestroy(b->execs[i]);
+    if (b->graphs && b->graphs[i]) (void)hipGraphDestroy(b->graphs[i]);
+    if (b->join && b->join[i]) (void)hipEventDestroy(b->join[i]);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  delete[] b->streams;
+  delete[] b->graphs;
+  delete[] b->execs;
+  delete[] b->join;
+  delete b;
+}
+
+// One member captured on its own plan stream (as rcqr_graph_create does).
+static rcqr_status_t capture_member(rcqr_plan_t p, int32_t method, const double* V, int64_t ldv, double* Q, int64_t ldq, double* R,
+                                    int64_t ldr, hipGraph_t* graph, hipGraphExec_t* exec) {
+  const int cap = p->cap;
+  p->cap = 0;  // no timing events inside the graph
+  if (hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    p->cap = cap;
+    return RCQR_E_HIP;
+  }
+  const rcqr_status_t sc = run_method(p, method, V, ldv, Q, ldq, R, ldr);
+  const hipError_t ec = hipStreamEndCapture(p->stream, graph);
+  p->cap = cap;
+  if (sc != RCQR_OK) return sc;
+  if (ec != hipSuccess || *graph == nullptr) return RCQR_E_HIP;
+  if (hipGraphInstantiate(exec, *graph, nullptr, nullptr, 0) != hipSuccess) return RCQR_E_HIP;
+  return RCQR_OK;
+}
+
+rcqr_status_t rcqr_batch_create(int32_t count, const rcqr_plan_t* plans, int32_t method, const double* const* V, const int64_t* ldv,
+                                double* const* Q, const int64_t* ldq, double* const* R, const int64_t* ldr, rcqr_batch_t* out) {
+  if (out == nullptr) return RCQR_E_INVALID;
+  *out = nullptr;
+  if (count < 1 || plans == nullptr || V == nullptr || ldv == nullptr || Q == nullptr || ldq == nullptr || R == nullptr ||
+      ldr == nullptr)
+    return RCQR_E_INVALID;
+  if (method < RCQR_METHOD_RAND_CHOLQR || method > RCQR_METHOD_SCHOLQR3) return RCQR_E_INVALID;
+  for (int32_t i = 0; i < count; ++i) {
+    const rcqr_plan_t p = plans[i];
+    if (p == nullptr || p->stream == nullptr) return RCQR_E_INVALID;
+    for (int32_t k = 0; k < i; ++k)
+      if (plans[k] == p) return RCQR_E_INVALID;
+    const rcqr_status_t st = check_io(p, V[i], ldv[i], Q[i], ldq[i], R[i], ldr[i]);
+    if (st != RCQR_OK) return st;
+  }
+  // host-side, one-time setup outside the captures
+  for (int32_t i = 0; i < count; ++i) RCQR_TRY(prepare_cholesky(plans[i]->sh.np));
+  RCQR_TRY(prepare_stream_launches());
+  rcqr_batch_s* b = new (std::nothrow) rcqr_batch_s();
+  if (b == nullptr) return RCQR_E_NOMEM;
+  b->count = count;
+  b->s0 = plans[0]->stream;
+  b->streams = new (std::nothrow) hipStream_t[count]();
+  b->graphs = new (std::nothrow) hipGraph_t[count]();
+  b->execs = new (std::nothrow) hipGraphExec_t[count]();
+  b->join = new (std::nothrow) hipEvent_t[count]();
+  if (!b->streams || !b->graphs || !b->execs || !b->join) {
+    free_batch(b);
+    return RCQR_E_NOMEM;
+  }
+  rcqr_status_t sc = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess ? RCQR_OK : RCQR_E_HIP;
+  for (int32_t i = 0; i < count && sc == RCQR_OK; ++i) {
+    b->streams[i] = plans[i]->stream;
+    if (hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming) != hipSuccess) sc = RCQR_E_HIP;
+    if (sc == RCQR_OK) sc = capture_member(plans[i], method, V[i], ldv[i], Q[i], ldq[i], R[i], ldr[i], &b->graphs[i], &b->execs[i]);
+  }
+  if (sc != RCQR_OK) {
+    free_batch(b);
+    return sc;
+  }
+  *out = b;
+  return RCQR_OK;
+}
+
+rcqr_status_t rcqr_batch_launch(rcqr_batch_t b) {
+  if (b == nullptr) return RCQR_E_INVALID;
+  RCQR_TRY(hipEventRecord(b->fork, b->s0));
+  for (int32_t i = 0; i < b->count; ++i) {
+    const bool side = b->streams[i] != b->s0;
+    if (side) RCQR_TRY(hipStreamWaitEvent(b->streams[i], b->fork, 0));
+    RCQR_TRY(hipGraphLaunch(b->execs[i], b->streams[i]));
+    if (side) {
+      RCQR_TRY(hipEventRecord(b->join[i], b->streams[i]));
+      RCQR_TRY(hipStreamWaitEvent(b->s0, b->join[i], 0));
+    }
+  }
+  return RCQR_OK;
+}
+
+rcqr_status_t rcqr_batch_destroy(rcqr_batch_t b) {
+  if (b == nullptr) return RCQR_E_INVALID;
+  free_batch(b);
+  return RCQR_OK;
+}
+
 rcqr_status_t rcqr_q0_twice(rcqr_plan_t p, const double* V, int64_t ldv, double* Q0a, double* Q0b, int64_t ldq) {
   if (p == nullptr || V == nullptr || Q0a == nullptr || Q0b == nullptr || ldv < p->sh.n || ldq < p->sh.n) return RCQR_E_INVALID;
   const Shape& sh = p->sh;

@@ -107,6 +107,23 @@ def test_plan_rejects_bad_arguments_on_host(lib):
         assert lib.rcqr_destroy(h) == rc.OK
     assert lib.rcqr_graph_launch(None) == rc.E_INVALID
     assert lib.rcqr_graph_destroy(None) == rc.E_INVALID
+    # batches: host-side argument checks (no plan on a capturable stream is needed for these)
+    b = ctypes.c_void_p()
+    P1 = (ctypes.c_void_p * 1)()
+    ptrs = (ctypes.c_void_p * 1)(p.value)
+    lds = (ctypes.c_int64 * 1)(16)
+    assert lib.rcqr_batch_create(0, P1, 0, ptrs, lds, ptrs, lds, ptrs, lds, ctypes.byref(b)) == rc.E_INVALID
+    assert lib.rcqr_batch_create(1, None, 0, ptrs, lds, ptrs, lds, ptrs, lds, ctypes.byref(b)) == rc.E_INVALID
+    assert lib.rcqr_batch_create(1, P1, 0, ptrs, lds, ptrs, lds, ptrs, lds, None) == rc.E_INVALID
+    assert lib.rcqr_plan(ctypes.byref(h), 1000, 16, 512, 64, 0, 0, ctypes.c_void_p(1 << 20), ws, None) == rc.OK
+    try:
+        P1[0] = h.value
+        assert lib.rcqr_batch_create(1, P1, 0, ptrs, lds, ptrs, lds, ptrs, lds, ctypes.byref(b)) == rc.E_INVALID  # default stream
+        assert lib.rcqr_batch_create(1, P1, 5, ptrs, lds, ptrs, lds, ptrs, lds, ctypes.byref(b)) == rc.E_INVALID  # method
+    finally:
+        assert lib.rcqr_destroy(h) == rc.OK
+    assert lib.rcqr_batch_launch(None) == rc.E_INVALID
+    assert lib.rcqr_batch_destroy(None) == rc.E_INVALID
 
 
 def test_binding_refuses_cpu_tensors(lib):
