@@ -55,6 +55,8 @@ _SIGNATURES = {
                                    ctypes.POINTER(_c_p), ctypes.POINTER(_c_i64), ctypes.POINTER(_c_p), ctypes.POINTER(_c_i64),
                                    ctypes.POINTER(_c_p)]),
     "rcqr_batch_launch": (_c_i32, [_c_p]),
+    "rcqr_factor_batch": (_c_i32, [_c_p, _c_i32, _c_p, _c_i64, _c_i64, _c_p, _c_i64, _c_i64, _c_p, _c_i64, _c_i64]),
+    "rcqr_info_member": (_c_i32, [_c_p, _c_i32, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32)]),
     "rcqr_batch_destroy": (_c_i32, [_c_p]),
 }
 
@@ -120,13 +122,15 @@ class Plan:
     """A factorization plan for m x n inputs with CountSketch size s1, Gaussian size s2, seed
     (flags: FLAG_* bits, 0 = all FP64)."""
 
-    def __init__(self, m, n, s1, s2, seed, device=None, stream=None, flags=0):
+    def __init__(self, m, n, s1, s2, seed, device=None, stream=None, flags=0, batch=1):
         self.m, self.n, self.s1, self.s2, self.seed = int(m), int(n), int(s1), int(s2), int(seed)
         self.flags = int(flags)
+        self.batch = int(batch)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         nbytes = workspace_bytes(self.m, self.n, self.s1, self.s2, self.flags)
-        if nbytes == 0:
+        if nbytes == 0 or self.batch < 1:
             raise RcqrError(E_UNSUPPORTED if 0 < n and n > MAX_N else E_INVALID, "rcqr_workspace_bytes")
+        nbytes *= self.batch  # one workspace slice per batch member (factor_batch)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         handle = ctypes.c_void_p()
@@ -210,6 +214,29 @@ class Plan:
 
     def set_tuning(self, final_mode, grid_mult):
         _check(lib().rcqr_set_tuning(self._h, int(final_mode), int(grid_mult)), "rcqr_set_tuning")
+
+    def factor_batch(self, V, Q=None, R=None):
+        """rcqr_factor_batch: V of shape (count, m, n), count <= the plan's batch; member b uses the
+        seed (plan seed + b).  Returns (Q, R) of shapes (count, m, n) and (count, n, n)."""
+        if V.dim() != 3 or V.shape[1:] != (self.m, self.n) or V.dtype != torch.float64 or not V.is_cuda:
+            raise ValueError("V must be a CUDA float64 tensor of shape (count, m, n)")
+        k = V.shape[0]
+        if Q is None:
+            Q = torch.empty_like(V)
+        if R is None:
+            R = torch.empty((k, self.n, self.n), dtype=torch.float64, device=V.device)
+        for t, nm in ((V, "V"), (Q, "Q"), (R, "R")):
+            if t.stride(2) != 1:
+                raise ValueError(f"{nm} rows must be contiguous")
+        _check(lib().rcqr_factor_batch(self._h, k, ctypes.c_void_p(V.data_ptr()), V.stride(1), V.stride(0),
+                                       ctypes.c_void_p(Q.data_ptr()), Q.stride(1), Q.stride(0),
+                                       ctypes.c_void_p(R.data_ptr()), R.stride(1), R.stride(0)), "rcqr_factor_batch")
+        return Q, R
+
+    def info_member(self, b):
+        st, col = _c_i32(), _c_i32()
+        _check(lib().rcqr_info_member(self._h, int(b), ctypes.byref(st), ctypes.byref(col)), "rcqr_info_member")
+        return st.value, col.value
 
     def graph(self, V, Q=None, R=None, method="rand_cholqr"):
         """Capture one factorization of V into (Q, R) as a HIP graph; returns a Graph whose

@@ -17,6 +17,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kQrRows = 256;     // rows one Householder workgroup factors
+constexpr int kMaxBatch = 4096;  // members of one rcqr_factor_batch call (a grid dimension)
 constexpr int kPhases = 7;
 constexpr int64_t kMaxRows = (int64_t)1 << 31;
 
@@ -139,6 +140,7 @@ struct rcqr_plan_s {
   uint32_t flags;
   hipStream_t stream;
   char* ws;
+  size_t ws_bytes;
   // launch choices that never change results (set by rcqr_tune or rcqr_set_tuning)
   int final_mode;  // RCQR_FINAL_RECOMPUTE or RCQR_FINAL_MATERIALIZE
   int grid_mult;   // workgroups-per-CU cap of the multi-row passes
@@ -309,6 +311,7 @@ rcqr_status_t rcqr_plan(rcqr_plan_t* plan, int64_t m, int64_t n, int64_t s1, int
   p->flags = flags;
   p->stream = reinterpret_cast<hipStream_t>(stream);
   p->ws = reinterpret_cast<char*>(d_workspace);
+  p->ws_bytes = workspace_bytes;
   p->final_mode = RCQR_FINAL_RECOMPUTE;
   p->grid_mult = 2;
   p->cap = 0;
@@ -433,6 +436,70 @@ rcqr_status_t rcqr_factor(rcqr_plan_t p, const double* V, int64_t ldv, double* Q
   }
   if (mark(p, 7) != RCQR_OK) return RCQR_E_HIP;
   if (p->cap > 0) ++p->recorded;
+  return RCQR_OK;
+}
+
+rcqr_status_t rcqr_factor_batch(rcqr_plan_t p, int32_t count, const double* V, int64_t ldv, int64_t sv, double* Q, int64_t ldq,
+                                int64_t sq, double* R, int64_t ldr, int64_t sr) {
+  const rcqr_status_t st = check_io(p, V, ldv, Q, ldq, R, ldr);
+  if (st != RCQR_OK) return st;
+  const Shape& sh = p->sh;
+  const Layout& L = p->L;
+  if (count < 1 || (size_t)count > p->ws_bytes / L.total) return RCQR_E_INVALID;
+  // members must not overlap (Q may be V itself, member by member)
+  if (sv < sh.m * ldv || sq < sh.m * ldq || sr < sh.n * ldr) return RCQR_E_INVALID;
+  if ((const void*)Q == (const void*)V && sq != sv) return RCQR_E_INVALID;
+  if (sh.np > 64 || sh.s2 > kQrRows || p->flags != 0 || count > kMaxBatch) return RCQR_E_UNSUPPORTED;
+  const int n = (int)sh.n;
+  hipStream_t s = p->stream;
+  MemberStride ms;
+  ms.ws = (int64_t)L.total;
+  ms.v = sv;
+  ms.q = sq;
+  ms.r = sr;
+  ms.count = count;
+  int32_t* info = p->at<int32_t>(L.info);
+  // the steps of rcqr_factor on the small-sketch FP64 path, each one launch for all members
+  RCQR_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(info), 16, 0u, s, count, ms.ws / 4));
+  if (sh.lds_cs) {
+    RCQR_TRY(launch_countsketch_lds(V, ldv, sh.m, n, sh.s1, p->seed, p->at<double>(L.csparts), sh.cs_parts, s, ms));
+    RCQR_TRY(launch_reduce_parts(p->at<double>(L.csparts), sh.cs_parts, sh.s1 * sh.n, sh.s1 * sh.n, p->at<double>(L.w1), s, ms));
+  } else {
+    uint32_t* counts = p->at<uint32_t>(L.counts);
+    uint32_t* offsets = p->at<uint32_t>(L.offsets);
+    uint32_t* hist = p->at<uint32_t>(L.hist);
+    uint32_t* codes = p->at<uint32_t>(L.codes);
+    uint32_t* entries = p->at<uint32_t>(L.entries);
+    uint8_t* unsorted = p->at<uint8_t>(L.unsorted);
+    RCQR_TRY(launch_hash_hist(sh.m, sh.s1, p->seed, sh.nchunk, codes, hist, s, ms));
+    RCQR_TRY(launch_hist_colscan(sh.nchunk, sh.s1, hist, counts, unsorted, s, ms));
+    RCQR_TRY(launch_bucket_scan(counts, sh.s1, offsets, nullptr, s, ms));
+    RCQR_TRY(launch_bucket_scatter(sh.m, sh.s1, sh.nchunk, codes, offsets, hist, entries, unsorted, s, ms));
+    RCQR_TRY(launch_bucket_gather(V, ldv, sh.m, n, sh.s1, offsets, entries, bucket_scatter_sorts(sh.s1) ? unsorted : nullptr,
+                                  p->at<double>(L.w1), s, ms));
+  }
+  const double scale = 1.0 / std::sqrt((double)sh.s2);
+  RCQR_TRY(launch_gauss_gemm(p->at<double>(L.w1), n, sh.s1, sh.s2, p->seed, scale, sh.kc_len, sh.nkc, p->at<double>(L.wpart), s, ms));
+  RCQR_TRY(launch_reduce_parts(p->at<double>(L.wpart), sh.nkc, sh.s2 * sh.n, sh.s2 * sh.n, p->at<double>(L.w), s, ms));
+  RCQR_TRY(launch_qr_blocks(p->at<double>(L.w), n, sh.s2, kQrRows, n, p->at<double>(L.qra), 1, s, ms));
+  RCQR_TRY(launch_finalize_r0(p->at<double>(L.qra), n, sh.np, info, p->at<double>(L.r0), p->at<double>(L.r0pk), s, ms));
+  RCQR_TRY(launch_trsm_gram(sh.np, V, sh.m, n, ldv, p->at<double>(L.r0pk), info, p->at<double>(L.gpart), nullptr, ldq, s, ms));
+  const int64_t len = gram_compact_len(sh.np);
+  RCQR_TRY(launch_reduce_parts(p->at<double>(L.gpart), kGramBlocks, len, len, p->at<double>(L.gc), s, ms));
+  RCQR_TRY(launch_cholesky(p->at<double>(L.gc), n, sh.np, p->at<double>(L.r0), 0.0, info, p->at<double>(L.g), p->at<double>(L.r1),
+                           p->at<double>(L.r1pk), R, ldr, s, ms));
+  RCQR_TRY(launch_final(sh.np, true, V, sh.m, n, ldv, p->at<double>(L.r0pk), p->at<double>(L.r1pk), info, Q, ldq, s, p->grid_mult, ms));
+  return RCQR_OK;
+}
+
+rcqr_status_t rcqr_info_member(rcqr_plan_t p, int32_t member, int32_t* status, int32_t* column) {
+  if (p == nullptr || status == nullptr || column == nullptr || member < 0 || (size_t)member >= p->ws_bytes / p->L.total)
+    return RCQR_E_INVALID;
+  int32_t h[2] = {0, 0};
+  RCQR_TRY(hipMemcpyAsync(h, p->ws + (size_t)member * p->L.total + p->L.info, sizeof(h), hipMemcpyDeviceToHost, p->stream));
+  RCQR_TRY(hipStreamSynchronize(p->stream));
+  *status = h[0];
+  *column = h[1];
   return RCQR_OK;
 }
 

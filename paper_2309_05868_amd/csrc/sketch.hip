@@ -7,8 +7,8 @@
 //     lowest such lane, in row order; the copies are summed in fixed order.
 //   * otherwise: a bucket index (CSR of S1) is built per call -- hash codes, bucket counts,
 //     exclusive scan, scatter of (row, sign) -- and one wave per bucket gathers its rows.  The
-//     wave sorts its bucket's entries by row before summing, so the sum order is ascending
-//     row order whatever order the scatter's atomics produced.
+//     scatter sorts each chunk's short segment of each bucket (or the gather sorts the bucket),
+//     so the sum order is ascending row order whatever order the scatter's atomics produced.
 // The Gaussian sketch S2 = G / sqrt(s2) (Section 3) is never stored: each GEMM workgroup
 // regenerates its 64 x 16 tiles of S2 from Philox counters in LDS.
 #include "device_common.h"
@@ -19,7 +19,8 @@ namespace rcqr {
 // ------------------------------------------------------------------------------------------
 // fills
 // ------------------------------------------------------------------------------------------
-__global__ void fill_u32_kernel(uint32_t* p, int64_t count, uint32_t v) {
+__global__ void fill_u32_kernel(uint32_t* p, int64_t count, uint32_t v, int64_t member_words) {
+  p += blockIdx.y * member_words;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
 __global__ void fill_f64_kernel(double* p, int64_t count, double v) {
@@ -33,9 +34,9 @@ static int grid_for(int64_t count, int threads, int cap = 4096) {
   return (int)g;
 }
 
-hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t s) {
-  if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(count, 256)), dim3(256), 0, s, p, count, value);
+hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t s, int members, int64_t member_words) {
+  if (count <= 0 || members < 1) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(count, 256), members), dim3(256), 0, s, p, count, value, member_words);
   return hipGetLastError();
 }
 hipError_t launch_fill_f64(double* p, int64_t count, double value, hipStream_t s) {
@@ -54,8 +55,14 @@ constexpr int kHistLds = 16384;  // buckets counted in LDS; above this, in the c
 int64_t bucket_chunk_rows(int64_t m, int nchunk) { return ((m + nchunk - 1) / nchunk + 3) / 4 * 4; }
 
 __global__ __launch_bounds__(256) void hash_hist_kernel(int64_t m, uint64_t s1, uint64_t seed, int64_t chunk_rows, uint32_t* __restrict__ codes,
-                                                        uint32_t* __restrict__ hist) {
+                                                        uint32_t* __restrict__ hist, int64_t member_bytes) {
   __shared__ uint32_t lh[kHistLds];
+  {
+    const int64_t mb = blockIdx.y;  // batch member
+    codes = member_ptr(codes, mb * member_bytes);
+    hist = member_ptr(hist, mb * member_bytes);
+    seed += (uint64_t)mb;
+  }
   const bool in_lds = s1 <= (uint64_t)kHistLds;
   uint32_t* gh = hist + (int64_t)blockIdx.x * (int64_t)s1;
   if (in_lds) {
@@ -88,9 +95,12 @@ __global__ __launch_bounds__(256) void hash_hist_kernel(int64_t m, uint64_t s1, 
   }
 }
 
-hipError_t launch_hash_hist(int64_t m, int64_t s1, uint64_t seed, int nchunk, uint32_t* codes, uint32_t* hist, hipStream_t s) {
+hipError_t launch_hash_hist(int64_t m, int64_t s1, uint64_t seed, int nchunk, uint32_t* codes, uint32_t* hist, hipStream_t s,
+                            const MemberStride& ms) {
   if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(hash_hist_kernel, dim3(nchunk), dim3(256), 0, s, m, (uint64_t)s1, seed, bucket_chunk_rows(m, nchunk), codes, hist);
+  if (ms.count < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(hash_hist_kernel, dim3(nchunk, ms.count), dim3(256), 0, s, m, (uint64_t)s1, seed, bucket_chunk_rows(m, nchunk), codes,
+                     hist, ms.ws);
   return hipGetLastError();
 }
 
@@ -98,8 +108,14 @@ hipError_t launch_hash_hist(int64_t m, int64_t s1, uint64_t seed, int nchunk, ui
 // counts[b] <- total rows of bucket b.  Workgroup: 32 buckets x 8 chunk segments; each thread
 // scans its segment of one column, the segment totals are combined through LDS.
 __global__ __launch_bounds__(256) void hist_colscan_kernel(int nchunk, int64_t s1, uint32_t* __restrict__ hist, uint32_t* __restrict__ counts,
-                                                           uint8_t* __restrict__ unsorted) {
+                                                           uint8_t* __restrict__ unsorted, int64_t member_bytes) {
   constexpr int NB = 32, NS = 8, BATCH = 8;
+  {
+    const int64_t off = (int64_t)blockIdx.y * member_bytes;  // batch member
+    hist = member_ptr(hist, off);
+    counts = member_ptr(counts, off);
+    unsorted = member_ptr(unsorted, off);
+  }
   __shared__ uint32_t segtot[NS][NB];
   const int bl = threadIdx.x % NB, sg = threadIdx.x / NB;
   const int64_t b = (int64_t)blockIdx.x * NB + bl;
@@ -137,8 +153,11 @@ __global__ __launch_bounds__(256) void hist_colscan_kernel(int nchunk, int64_t s
   }
 }
 
-hipError_t launch_hist_colscan(int nchunk, int64_t s1, uint32_t* hist, uint32_t* counts, uint8_t* unsorted, hipStream_t s) {
-  hipLaunchKernelGGL(hist_colscan_kernel, dim3((unsigned)((s1 + 31) / 32)), dim3(256), 0, s, nchunk, s1, hist, counts, unsorted);
+hipError_t launch_hist_colscan(int nchunk, int64_t s1, uint32_t* hist, uint32_t* counts, uint8_t* unsorted, hipStream_t s,
+                               const MemberStride& ms) {
+  if (ms.count < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(hist_colscan_kernel, dim3((unsigned)((s1 + 31) / 32), ms.count), dim3(256), 0, s, nchunk, s1, hist, counts, unsorted,
+                     ms.ws);
   return hipGetLastError();
 }
 
@@ -166,8 +185,15 @@ hipError_t launch_hash_debug(int64_t row0, int64_t count, int64_t s1, uint64_t s
 // Tiles of 8192 counts: each thread scans 8 consecutive counts, the 1024 thread totals are
 // scanned by waves (shuffles) and across the 16 waves through LDS, plus the carry of earlier tiles.
 __global__ __launch_bounds__(1024) void bucket_scan_kernel(const uint32_t* __restrict__ counts, int64_t s1,
-                                                           uint32_t* __restrict__ offsets, uint32_t* __restrict__ cursor) {
+                                                           uint32_t* __restrict__ offsets, uint32_t* __restrict__ cursor,
+                                                           int64_t member_bytes) {
   constexpr int PER = 8;
+  {
+    const int64_t off = (int64_t)blockIdx.y * member_bytes;  // batch member
+    counts = member_ptr(counts, off);
+    offsets = member_ptr(offsets, off);
+    cursor = member_ptr(cursor, off);
+  }
   __shared__ uint32_t wsum[16];
   __shared__ uint32_t carry_s;
   const int t = threadIdx.x, lane = lane_id(), wave = t / kWave;
@@ -207,8 +233,10 @@ __global__ __launch_bounds__(1024) void bucket_scan_kernel(const uint32_t* __res
   if (t == 0) offsets[s1] = carry;
 }
 
-hipError_t launch_bucket_scan(const uint32_t* counts, int64_t s1, uint32_t* offsets, uint32_t* cursor, hipStream_t s) {
-  hipLaunchKernelGGL(bucket_scan_kernel, dim3(1), dim3(1024), 0, s, counts, s1, offsets, cursor);
+hipError_t launch_bucket_scan(const uint32_t* counts, int64_t s1, uint32_t* offsets, uint32_t* cursor, hipStream_t s,
+                              const MemberStride& ms) {
+  if (ms.count < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(bucket_scan_kernel, dim3(1, ms.count), dim3(1024), 0, s, counts, s1, offsets, cursor, ms.ws);
   return hipGetLastError();
 }
 
@@ -251,8 +279,16 @@ bool bucket_scatter_sorts(int64_t s1) { return s1 <= (int64_t)kHistLds; }
 // segments are left as they are and the gather sorts every bucket.
 __global__ __launch_bounds__(256) void bucket_scatter_kernel(int64_t m, int64_t s1, int64_t chunk_rows, const uint32_t* __restrict__ codes,
                                                              const uint32_t* __restrict__ offsets, uint32_t* __restrict__ hist,
-                                                             uint32_t* entries, uint8_t* __restrict__ unsorted) {
+                                                             uint32_t* entries, uint8_t* __restrict__ unsorted, int64_t member_bytes) {
   __shared__ uint32_t cur[kHistLds];
+  {
+    const int64_t off = (int64_t)blockIdx.y * member_bytes;  // batch member
+    codes = member_ptr(codes, off);
+    offsets = member_ptr(offsets, off);
+    hist = member_ptr(hist, off);
+    entries = member_ptr(entries, off);
+    unsorted = member_ptr(unsorted, off);
+  }
   __shared__ uint32_t seg0[kHistLds];  // start of this chunk's segment of each bucket
   const bool in_lds = s1 <= (int64_t)kHistLds;
   uint32_t* gh = hist + (int64_t)blockIdx.x * s1;
@@ -295,11 +331,11 @@ __global__ __launch_bounds__(256) void bucket_scatter_kernel(int64_t m, int64_t 
 }
 
 hipError_t launch_bucket_scatter(int64_t m, int64_t s1, int nchunk, const uint32_t* codes, const uint32_t* offsets, uint32_t* hist,
-                                 uint32_t* entries, uint8_t* unsorted, hipStream_t s) {
+                                 uint32_t* entries, uint8_t* unsorted, hipStream_t s, const MemberStride& ms) {
   if (m <= 0) return hipSuccess;
-  if (bucket_scatter_sorts(s1) && unsorted == nullptr) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(bucket_scatter_kernel, dim3(nchunk), dim3(256), 0, s, m, s1, bucket_chunk_rows(m, nchunk), codes, offsets, hist,
-                     entries, unsorted);
+  if ((bucket_scatter_sorts(s1) && unsorted == nullptr) || ms.count < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(bucket_scatter_kernel, dim3(nchunk, ms.count), dim3(256), 0, s, m, s1, bucket_chunk_rows(m, nchunk), codes, offsets,
+                     hist, entries, unsorted, ms.ws);
   return hipGetLastError();
 }
 
@@ -388,8 +424,16 @@ template <int NPL, class T>
 __global__ __launch_bounds__(256) void bucket_gather_kernel(const double* __restrict__ V, int64_t ldv, int64_t m, int n, int64_t s1,
                                                             const uint32_t* __restrict__ offsets,
                                                             const uint32_t* __restrict__ entries,
-                                                            const uint8_t* __restrict__ unsorted, T* __restrict__ W1) {
+                                                            const uint8_t* __restrict__ unsorted, T* __restrict__ W1, MemberStride ms) {
   __shared__ uint32_t keys_all[kGatherWaves][kSortCap];
+  {
+    const int64_t mb = blockIdx.y, off = mb * ms.ws;  // batch member
+    V += mb * ms.v;
+    offsets = member_ptr(offsets, off);
+    entries = member_ptr(entries, off);
+    unsorted = member_ptr(unsorted, off);
+    W1 = member_ptr(W1, off);
+  }
   const int wave = threadIdx.x / kWave;
   const int lane = lane_id();
   const int64_t b = (int64_t)blockIdx.x * kGatherWaves + wave;
@@ -476,29 +520,31 @@ __global__ __launch_bounds__(256) void bucket_gather_kernel(const double* __rest
 
 template <class T>
 static hipError_t bucket_gather_any(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, const uint32_t* offsets,
-                                    const uint32_t* entries, const uint8_t* unsorted, T* W1, hipStream_t s) {
-  const dim3 grid((unsigned)((s1 + kGatherWaves - 1) / kGatherWaves)), block(256);
+                                    const uint32_t* entries, const uint8_t* unsorted, T* W1, hipStream_t s,
+                                    const MemberStride& ms) {
+  if (ms.count < 1) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((s1 + kGatherWaves - 1) / kGatherWaves), ms.count), block(256);
   if (n <= 8)
-    hipLaunchKernelGGL((bucket_gather_kernel<8, T>), grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, unsorted, W1);
+    hipLaunchKernelGGL((bucket_gather_kernel<8, T>), grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, unsorted, W1, ms);
   else if (n <= 16)
-    hipLaunchKernelGGL((bucket_gather_kernel<16, T>), grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, unsorted, W1);
+    hipLaunchKernelGGL((bucket_gather_kernel<16, T>), grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, unsorted, W1, ms);
   else if (n <= 32)
-    hipLaunchKernelGGL((bucket_gather_kernel<32, T>), grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, unsorted, W1);
+    hipLaunchKernelGGL((bucket_gather_kernel<32, T>), grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, unsorted, W1, ms);
   else if (n <= 64)
-    hipLaunchKernelGGL((bucket_gather_kernel<64, T>), grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, unsorted, W1);
+    hipLaunchKernelGGL((bucket_gather_kernel<64, T>), grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, unsorted, W1, ms);
   else
-    hipLaunchKernelGGL((bucket_gather_kernel<128, T>), grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, unsorted, W1);
+    hipLaunchKernelGGL((bucket_gather_kernel<128, T>), grid, block, 0, s, V, ldv, m, n, s1, offsets, entries, unsorted, W1, ms);
   return hipGetLastError();
 }
 
 hipError_t launch_bucket_gather(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, const uint32_t* offsets,
-                                const uint32_t* entries, const uint8_t* unsorted, double* W1, hipStream_t s) {
-  return bucket_gather_any(V, ldv, m, n, s1, offsets, entries, unsorted, W1, s);
+                                const uint32_t* entries, const uint8_t* unsorted, double* W1, hipStream_t s, const MemberStride& ms) {
+  return bucket_gather_any(V, ldv, m, n, s1, offsets, entries, unsorted, W1, s, ms);
 }
 
 hipError_t launch_bucket_gather(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, const uint32_t* offsets,
                                 const uint32_t* entries, const uint8_t* unsorted, float* W1, hipStream_t s) {
-  return bucket_gather_any(V, ldv, m, n, s1, offsets, entries, unsorted, W1, s);
+  return bucket_gather_any(V, ldv, m, n, s1, offsets, entries, unsorted, W1, s, MemberStride());
 }
 
 // ------------------------------------------------------------------------------------------
@@ -534,8 +580,14 @@ int countsketch_lds_parts(int64_t m, int64_t s1, int n) {
 
 template <int NPL, class T, int CAP>
 __global__ __launch_bounds__(256) void countsketch_lds_kernel(const double* __restrict__ V, int64_t ldv, int64_t m, int n, int64_t s1,
-                                                              uint64_t seed, T* __restrict__ parts) {
+                                                              uint64_t seed, T* __restrict__ parts, MemberStride ms) {
   __shared__ T w1[4][CAP];
+  {
+    const int64_t mb = blockIdx.y;  // batch member
+    V += mb * ms.v;
+    parts = member_ptr(parts, mb * ms.ws);
+    seed += (uint64_t)mb;
+  }
   __shared__ uint32_t codes[4][kCsChunk];
   constexpr int RB = kWave / NPL;  // rows per batch
   const int wave = threadIdx.x / kWave, lane = lane_id();
@@ -610,40 +662,40 @@ __global__ __launch_bounds__(256) void countsketch_lds_kernel(const double* __re
 
 template <int NPL, class T>
 static void countsketch_lds_cap(int cap, dim3 grid, hipStream_t s, const double* V, int64_t ldv, int64_t m, int n, int64_t s1,
-                                uint64_t seed, T* parts) {
+                                uint64_t seed, T* parts, const MemberStride& ms) {
   const dim3 block(256);
   if (cap == 1024)
-    hipLaunchKernelGGL((countsketch_lds_kernel<NPL, T, 1024>), grid, block, 0, s, V, ldv, m, n, s1, seed, parts);
+    hipLaunchKernelGGL((countsketch_lds_kernel<NPL, T, 1024>), grid, block, 0, s, V, ldv, m, n, s1, seed, parts, ms);
   else if (cap == 2048)
-    hipLaunchKernelGGL((countsketch_lds_kernel<NPL, T, 2048>), grid, block, 0, s, V, ldv, m, n, s1, seed, parts);
+    hipLaunchKernelGGL((countsketch_lds_kernel<NPL, T, 2048>), grid, block, 0, s, V, ldv, m, n, s1, seed, parts, ms);
   else
-    hipLaunchKernelGGL((countsketch_lds_kernel<NPL, T, 4096>), grid, block, 0, s, V, ldv, m, n, s1, seed, parts);
+    hipLaunchKernelGGL((countsketch_lds_kernel<NPL, T, 4096>), grid, block, 0, s, V, ldv, m, n, s1, seed, parts, ms);
 }
 
 template <class T>
 static hipError_t countsketch_lds_any(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, uint64_t seed, T* parts,
-                                      int nparts, hipStream_t s) {
-  if (!countsketch_lds_fits(s1, n) || nparts < 1) return hipErrorInvalidValue;
-  const dim3 grid(nparts);
+                                      int nparts, hipStream_t s, const MemberStride& ms) {
+  if (!countsketch_lds_fits(s1, n) || nparts < 1 || ms.count < 1) return hipErrorInvalidValue;
+  const dim3 grid(nparts, ms.count);
   const int cap = cs_cap(s1, n);
   switch (npl_of(n)) {
-    case 8: countsketch_lds_cap<8, T>(cap, grid, s, V, ldv, m, n, s1, seed, parts); break;
-    case 16: countsketch_lds_cap<16, T>(cap, grid, s, V, ldv, m, n, s1, seed, parts); break;
-    case 32: countsketch_lds_cap<32, T>(cap, grid, s, V, ldv, m, n, s1, seed, parts); break;
-    case 64: countsketch_lds_cap<64, T>(cap, grid, s, V, ldv, m, n, s1, seed, parts); break;
+    case 8: countsketch_lds_cap<8, T>(cap, grid, s, V, ldv, m, n, s1, seed, parts, ms); break;
+    case 16: countsketch_lds_cap<16, T>(cap, grid, s, V, ldv, m, n, s1, seed, parts, ms); break;
+    case 32: countsketch_lds_cap<32, T>(cap, grid, s, V, ldv, m, n, s1, seed, parts, ms); break;
+    case 64: countsketch_lds_cap<64, T>(cap, grid, s, V, ldv, m, n, s1, seed, parts, ms); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_countsketch_lds(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, uint64_t seed, double* parts,
-                                  int nparts, hipStream_t s) {
-  return countsketch_lds_any(V, ldv, m, n, s1, seed, parts, nparts, s);
+                                  int nparts, hipStream_t s, const MemberStride& ms) {
+  return countsketch_lds_any(V, ldv, m, n, s1, seed, parts, nparts, s, ms);
 }
 
 hipError_t launch_countsketch_lds(const double* V, int64_t ldv, int64_t m, int n, int64_t s1, uint64_t seed, float* parts,
                                   int nparts, hipStream_t s) {
-  return countsketch_lds_any(V, ldv, m, n, s1, seed, parts, nparts, s);
+  return countsketch_lds_any(V, ldv, m, n, s1, seed, parts, nparts, s, MemberStride());
 }
 
 // ------------------------------------------------------------------------------------------
@@ -763,7 +815,13 @@ hipError_t launch_gauss_mfma(const float* W1, int n, int64_t s1, int64_t s2, uin
 // FP64 product: 8 v_mfma_f64_16x16x4f64 per 32-wide k step and 16-column block.
 template <int NP>
 __global__ __launch_bounds__(256) void gauss_mfma64_kernel(const double* __restrict__ W1, int n, int64_t s1, int64_t s2, uint64_t seed,
-                                                           double scale, int64_t kc_len, double* __restrict__ wpart) {
+                                                           double scale, int64_t kc_len, double* __restrict__ wpart, MemberStride ms) {
+  {
+    const int64_t mb = blockIdx.z;  // batch member
+    W1 = member_ptr(W1, mb * ms.ws);
+    wpart = member_ptr(wpart, mb * ms.ws);
+    seed += (uint64_t)mb;
+  }
   __shared__ double st[kGemmRows][kMmK + 1];  // S2 tile, [row j][k]
   __shared__ double wt[NP][kMmK + 1];         // W1 tile transposed, [column c][k]
   constexpr int NCB = NP / 16;
@@ -824,19 +882,19 @@ __global__ __launch_bounds__(256) void gauss_mfma64_kernel(const double* __restr
 
 template <int NP>
 static void launch_gauss64(dim3 grid, const double* W1, int n, int64_t s1, int64_t s2, uint64_t seed, double scale, int64_t kc_len,
-                           double* wpart, hipStream_t s) {
-  hipLaunchKernelGGL((gauss_mfma64_kernel<NP>), grid, dim3(256), 0, s, W1, n, s1, s2, seed, scale, kc_len, wpart);
+                           double* wpart, hipStream_t s, const MemberStride& ms) {
+  hipLaunchKernelGGL((gauss_mfma64_kernel<NP>), grid, dim3(256), 0, s, W1, n, s1, s2, seed, scale, kc_len, wpart, ms);
 }
 
 hipError_t launch_gauss_gemm(const double* W1, int n, int64_t s1, int64_t s2, uint64_t seed, double scale, int64_t kc_len,
-                             int64_t nkc, double* wpart, hipStream_t s) {
-  if (kc_len % kMmK != 0) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)nkc, (unsigned)((s2 + kGemmRows - 1) / kGemmRows));
+                             int64_t nkc, double* wpart, hipStream_t s, const MemberStride& ms) {
+  if (kc_len % kMmK != 0 || ms.count < 1) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)nkc, (unsigned)((s2 + kGemmRows - 1) / kGemmRows), ms.count);
   const int np = n <= 16 ? 16 : n <= 32 ? 32 : n <= 64 ? 64 : 128;
-  if (np == 16) launch_gauss64<16>(grid, W1, n, s1, s2, seed, scale, kc_len, wpart, s);
-  else if (np == 32) launch_gauss64<32>(grid, W1, n, s1, s2, seed, scale, kc_len, wpart, s);
-  else if (np == 64) launch_gauss64<64>(grid, W1, n, s1, s2, seed, scale, kc_len, wpart, s);
-  else launch_gauss64<128>(grid, W1, n, s1, s2, seed, scale, kc_len, wpart, s);
+  if (np == 16) launch_gauss64<16>(grid, W1, n, s1, s2, seed, scale, kc_len, wpart, s, ms);
+  else if (np == 32) launch_gauss64<32>(grid, W1, n, s1, s2, seed, scale, kc_len, wpart, s, ms);
+  else if (np == 64) launch_gauss64<64>(grid, W1, n, s1, s2, seed, scale, kc_len, wpart, s, ms);
+  else launch_gauss64<128>(grid, W1, n, s1, s2, seed, scale, kc_len, wpart, s, ms);
   return hipGetLastError();
 }
 
@@ -883,8 +941,10 @@ hipError_t launch_gaussian_block(int64_t j0, int64_t nj, int64_t k0, int64_t nk,
 // depends only on nparts, so the order of every sum is fixed.
 template <class T>
 __global__ __launch_bounds__(256) void reduce_parts_kernel(const T* __restrict__ parts, int64_t nparts, int64_t stride, int64_t len,
-                                                           T* __restrict__ out) {
+                                                           T* __restrict__ out, int64_t member_bytes) {
   constexpr int E = 16, G = 16;
+  parts = member_ptr(parts, (int64_t)blockIdx.y * member_bytes);
+  out = member_ptr(out, (int64_t)blockIdx.y * member_bytes);
   __shared__ T ssum[G][E], scomp[G][E];
   const int e = threadIdx.x % E, g = threadIdx.x / E;
   const int64_t i = (int64_t)blockIdx.x * E + e;
@@ -925,15 +985,18 @@ __global__ __launch_bounds__(256) void reduce_parts_kernel(const T* __restrict__
   }
 }
 
-hipError_t launch_reduce_parts(const double* parts, int64_t nparts, int64_t stride, int64_t len, double* out, hipStream_t s) {
-  if (len <= 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_parts_kernel<double>, dim3((unsigned)((len + 15) / 16)), dim3(256), 0, s, parts, nparts, stride, len, out);
+hipError_t launch_reduce_parts(const double* parts, int64_t nparts, int64_t stride, int64_t len, double* out, hipStream_t s,
+                               const MemberStride& ms) {
+  if (len <= 0 || ms.count < 1) return hipSuccess;
+  hipLaunchKernelGGL(reduce_parts_kernel<double>, dim3((unsigned)((len + 15) / 16), ms.count), dim3(256), 0, s, parts, nparts, stride, len,
+                     out, ms.ws);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_parts(const float* parts, int64_t nparts, int64_t stride, int64_t len, float* out, hipStream_t s) {
   if (len <= 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_parts_kernel<float>, dim3((unsigned)((len + 15) / 16)), dim3(256), 0, s, parts, nparts, stride, len, out);
+  hipLaunchKernelGGL(reduce_parts_kernel<float>, dim3((unsigned)((len + 15) / 16)), dim3(256), 0, s, parts, nparts, stride, len, out,
+                     (int64_t)0);
   return hipGetLastError();
 }
 

@@ -34,8 +34,11 @@ constexpr int kQrWaves = 16;
 
 template <int NC, class T>
 __global__ __launch_bounds__(kQrWaves * kWave) void qr_block_kernel(const T* __restrict__ in, int64_t ldin, int64_t p_total,
-                                                                    int64_t rows_per_block, int n, T* __restrict__ out) {
+                                                                    int64_t rows_per_block, int n, T* __restrict__ out,
+                                                                    int64_t member_bytes) {
   constexpr int ER = kQrMaxRows / kWave;  // rows per lane
+  in = member_ptr(in, (int64_t)blockIdx.y * member_bytes);  // batch member
+  out = member_ptr(out, (int64_t)blockIdx.y * member_bytes);
   __shared__ T vbuf[2][kQrMaxRows];
   __shared__ T taub[2];
   const int wave = threadIdx.x / kWave, lane = lane_id();
@@ -154,28 +157,29 @@ __global__ __launch_bounds__(kQrWaves * kWave) void qr_block_kernel(const T* __r
 
 template <class T>
 static hipError_t qr_blocks_any(const T* in, int64_t ldin, int64_t p_total, int64_t rows_per_block, int n, T* out, int nblocks,
-                                hipStream_t s) {
-  if (rows_per_block > kQrMaxRows || n > RCQR_MAX_N || n < 1) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)nblocks), block(kQrWaves * kWave);
+                                hipStream_t s, const MemberStride& ms) {
+  if (rows_per_block > kQrMaxRows || n > RCQR_MAX_N || n < 1 || ms.count < 1) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)nblocks, ms.count), block(kQrWaves * kWave);
+  const int64_t mbytes = ms.ws;
   if (n <= 16)
-    hipLaunchKernelGGL((qr_block_kernel<1, T>), grid, block, 0, s, in, ldin, p_total, rows_per_block, n, out);
+    hipLaunchKernelGGL((qr_block_kernel<1, T>), grid, block, 0, s, in, ldin, p_total, rows_per_block, n, out, mbytes);
   else if (n <= 32)
-    hipLaunchKernelGGL((qr_block_kernel<2, T>), grid, block, 0, s, in, ldin, p_total, rows_per_block, n, out);
+    hipLaunchKernelGGL((qr_block_kernel<2, T>), grid, block, 0, s, in, ldin, p_total, rows_per_block, n, out, mbytes);
   else if (n <= 64)
-    hipLaunchKernelGGL((qr_block_kernel<4, T>), grid, block, 0, s, in, ldin, p_total, rows_per_block, n, out);
+    hipLaunchKernelGGL((qr_block_kernel<4, T>), grid, block, 0, s, in, ldin, p_total, rows_per_block, n, out, mbytes);
   else
-    hipLaunchKernelGGL((qr_block_kernel<8, T>), grid, block, 0, s, in, ldin, p_total, rows_per_block, n, out);
+    hipLaunchKernelGGL((qr_block_kernel<8, T>), grid, block, 0, s, in, ldin, p_total, rows_per_block, n, out, mbytes);
   return hipGetLastError();
 }
 
 hipError_t launch_qr_blocks(const double* in, int64_t ldin, int64_t p_total, int64_t rows_per_block, int n, double* out,
-                            int nblocks, hipStream_t s) {
-  return qr_blocks_any(in, ldin, p_total, rows_per_block, n, out, nblocks, s);
+                            int nblocks, hipStream_t s, const MemberStride& ms) {
+  return qr_blocks_any(in, ldin, p_total, rows_per_block, n, out, nblocks, s, ms);
 }
 
 hipError_t launch_qr_blocks(const float* in, int64_t ldin, int64_t p_total, int64_t rows_per_block, int n, float* out,
                             int nblocks, hipStream_t s) {
-  return qr_blocks_any(in, ldin, p_total, rows_per_block, n, out, nblocks, s);
+  return qr_blocks_any(in, ldin, p_total, rows_per_block, n, out, nblocks, s, MemberStride());
 }
 
 // Offset of row k in the packed np x np upper-triangular format.
@@ -208,8 +212,15 @@ __device__ __forceinline__ void put_packed(double* pk, int np, int n, int r, int
 // ------------------------------------------------------------------------------------------
 template <class T>
 __global__ __launch_bounds__(256) void finalize_r0_kernel(const T* __restrict__ rin, int n, int np, int32_t* __restrict__ info,
-                                                          double* __restrict__ r0, double* __restrict__ r0pk) {
+                                                          double* __restrict__ r0, double* __restrict__ r0pk, int64_t member_bytes) {
   __shared__ int bad;  // first failing column (1-based), or a value > n
+  {
+    const int64_t off = (int64_t)blockIdx.y * member_bytes;  // batch member
+    rin = member_ptr(rin, off);
+    info = member_ptr(info, off);
+    r0 = member_ptr(r0, off);
+    r0pk = member_ptr(r0pk, off);
+  }
   if (info[0] != 0) return;  // an earlier step failed: keep its status
   if (threadIdx.x == 0) bad = n + 1;
   __syncthreads();
@@ -235,13 +246,15 @@ __global__ __launch_bounds__(256) void finalize_r0_kernel(const T* __restrict__ 
   }
 }
 
-hipError_t launch_finalize_r0(const double* rin, int n, int np, int32_t* info, double* r0, double* r0pk, hipStream_t s) {
-  hipLaunchKernelGGL(finalize_r0_kernel<double>, dim3(1), dim3(256), 0, s, rin, n, np, info, r0, r0pk);
+hipError_t launch_finalize_r0(const double* rin, int n, int np, int32_t* info, double* r0, double* r0pk, hipStream_t s,
+                              const MemberStride& ms) {
+  if (ms.count < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(finalize_r0_kernel<double>, dim3(1, ms.count), dim3(256), 0, s, rin, n, np, info, r0, r0pk, ms.ws);
   return hipGetLastError();
 }
 
 hipError_t launch_finalize_r0(const float* rin, int n, int np, int32_t* info, double* r0, double* r0pk, hipStream_t s) {
-  hipLaunchKernelGGL(finalize_r0_kernel<float>, dim3(1), dim3(256), 0, s, rin, n, np, info, r0, r0pk);
+  hipLaunchKernelGGL(finalize_r0_kernel<float>, dim3(1), dim3(256), 0, s, rin, n, np, info, r0, r0pk, (int64_t)0);
   return hipGetLastError();
 }
 
@@ -292,8 +305,18 @@ __global__ __launch_bounds__(CholShape<NP>::NWV * kWave) void cholesky_kernel(co
                                                                               const double* __restrict__ rprev, double shift_coef,
                                                                               int32_t* __restrict__ info, double* __restrict__ g_out,
                                                                               double* __restrict__ r1, double* __restrict__ r1pk,
-                                                                              double* __restrict__ r_out, int64_t ldr) {
+                                                                              double* __restrict__ r_out, int64_t ldr, MemberStride ms) {
   constexpr int NWV = CholShape<NP>::NWV, CPL = CholShape<NP>::CPL, BR = CholShape<NP>::BR, NBT = CholShape<NP>::NBT;
+  {
+    const int64_t mb = blockIdx.y, off = mb * ms.ws;  // batch member
+    gc = member_ptr(gc, off);
+    rprev = member_ptr(rprev, off);
+    info = member_ptr(info, off);
+    g_out = member_ptr(g_out, off);
+    r1 = member_ptr(r1, off);
+    r1pk = member_ptr(r1pk, off);
+    r_out += mb * ms.r;
+  }
   constexpr int NB = NP / 16;
   extern __shared__ double Rl[];  // NP x NP, the rows of the LDL^T elimination; then Rprev (NP <= 64)
   double* rp = Rl + NP * NP;
@@ -516,22 +539,23 @@ hipError_t prepare_cholesky(int np) {
 
 template <int NP>
 static hipError_t cholesky_any(const double* gcompact, int n, const double* rprev, double shift_coef, int32_t* info, double* g_out,
-                               double* r1, double* r1pk, double* r_out, int64_t ldr, hipStream_t s) {
+                               double* r1, double* r1pk, double* r_out, int64_t ldr, hipStream_t s, const MemberStride& ms) {
   const hipError_t e = cholesky_prepare<NP>();
   if (e != hipSuccess) return e;
+  if (ms.count < 1) return hipErrorInvalidValue;
   const size_t lds = cholesky_lds<NP>();
-  hipLaunchKernelGGL(cholesky_kernel<NP>, dim3(1), dim3(CholShape<NP>::NWV * kWave), lds, s, gcompact, n, rprev, shift_coef, info,
-                     g_out, r1, r1pk, r_out, ldr);
+  hipLaunchKernelGGL(cholesky_kernel<NP>, dim3(1, ms.count), dim3(CholShape<NP>::NWV * kWave), lds, s, gcompact, n, rprev, shift_coef,
+                     info, g_out, r1, r1pk, r_out, ldr, ms);
   return hipGetLastError();
 }
 
 hipError_t launch_cholesky(const double* gcompact, int n, int np, const double* rprev, double shift_coef, int32_t* info,
-                           double* g_out, double* r1, double* r1pk, double* r_out, int64_t ldr, hipStream_t s) {
+                           double* g_out, double* r1, double* r1pk, double* r_out, int64_t ldr, hipStream_t s, const MemberStride& ms) {
   switch (np) {
-    case 16: return cholesky_any<16>(gcompact, n, rprev, shift_coef, info, g_out, r1, r1pk, r_out, ldr, s);
-    case 32: return cholesky_any<32>(gcompact, n, rprev, shift_coef, info, g_out, r1, r1pk, r_out, ldr, s);
-    case 64: return cholesky_any<64>(gcompact, n, rprev, shift_coef, info, g_out, r1, r1pk, r_out, ldr, s);
-    case 128: return cholesky_any<128>(gcompact, n, rprev, shift_coef, info, g_out, r1, r1pk, r_out, ldr, s);
+    case 16: return cholesky_any<16>(gcompact, n, rprev, shift_coef, info, g_out, r1, r1pk, r_out, ldr, s, ms);
+    case 32: return cholesky_any<32>(gcompact, n, rprev, shift_coef, info, g_out, r1, r1pk, r_out, ldr, s, ms);
+    case 64: return cholesky_any<64>(gcompact, n, rprev, shift_coef, info, g_out, r1, r1pk, r_out, ldr, s, ms);
+    case 128: return cholesky_any<128>(gcompact, n, rprev, shift_coef, info, g_out, r1, r1pk, r_out, ldr, s, ms);
     default: return hipErrorInvalidValue;
   }
 }

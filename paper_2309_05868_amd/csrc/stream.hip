@@ -127,14 +127,24 @@ int gram_compact_len(int np) {
   return nb * (nb + 1) / 2 * 256;
 }
 
-template <int NP, bool FULL, bool STORE>
+template <int NP, bool FULL, bool STORE, bool BATCH>
 __global__ __launch_bounds__(kGramThreads, 1) void trsm_gram_kernel(const double* __restrict__ V, int64_t m, int n, int64_t ldv,
                                                                     const double* __restrict__ R0pk,
                                                                     const int32_t* __restrict__ info, double* __restrict__ gpart,
-                                                                    double* __restrict__ q0, int64_t ldq) {
+                                                                    double* __restrict__ q0, int64_t ldq, MemberStride ms) {
   constexpr int NB = NP / 16;
   constexpr int NBU = NB * (NB + 1) / 2;
   constexpr int NW = kGramThreads / kWave;
+  if constexpr (BATCH) {
+    // batch member: workspace pointers move by whole doubles / ints (the workspace stride is a
+    // multiple of 256 bytes), keeping them typed so the factor still streams through scalar loads
+    const int64_t mb = blockIdx.y, off = mb * ms.ws;
+    V += mb * ms.v;
+    R0pk += off / (int64_t)sizeof(double);
+    info += off / (int64_t)sizeof(int32_t);
+    gpart += off / (int64_t)sizeof(double);
+    if (q0 != nullptr) q0 += mb * ms.q;
+  }
   __shared__ double xs[NW][16][kWave + 1];
   __shared__ double gl[NBU * 256];
   if (info[0] != 0) return;
@@ -273,13 +283,21 @@ __device__ __forceinline__ void build_rinv_blocks(const double* __restrict__ Rpk
 //     into MFMA operands, Q[16 rows] = X[16 rows] R1^{-1} on v_mfma_f64_16x16x4f64
 //     (upper blocks only), written straight from the accumulators.
 // Only R0 streams through the scalar data cache (R0 and R1 together would not fit it).
-template <int NP, bool FULL, int NW>
+template <int NP, bool FULL, int NW, bool BATCH>
 __global__ __launch_bounds__(NW * kWave) void final_mfma_kernel(const double* __restrict__ V, int64_t m, int n, int64_t ldv,
                                                                const double* __restrict__ R0pk, const double* __restrict__ R1pk,
                                                                const int32_t* __restrict__ info, double* __restrict__ Q,
-                                                               int64_t ldq) {
+                                                               int64_t ldq, MemberStride ms) {
   constexpr int NB = NP / 16;
   constexpr int NBU = NB * (NB + 1) / 2;
+  if constexpr (BATCH) {
+    const int64_t mb = blockIdx.y, off = mb * ms.ws;  // batch member (typed offsets, as above)
+    V += mb * ms.v;
+    R0pk += off / (int64_t)sizeof(double);
+    R1pk += off / (int64_t)sizeof(double);
+    info += off / (int64_t)sizeof(int32_t);
+    Q += mb * ms.q;
+  }
   __shared__ double rib[NBU * 256];
   __shared__ double st[NW][16][NP + 1];
   if (info[0] != 0) return;
@@ -470,18 +488,25 @@ static bool full_rows(int np, int n, const void* a, int64_t lda, const void* b, 
 }
 
 hipError_t launch_trsm_gram(int np, const double* V, int64_t m, int n, int64_t ldv, const double* r0pk, const int32_t* info,
-                            double* gpart, double* q0, int64_t ldq, hipStream_t s) {
-  const dim3 grid(kGramBlocks), block(kGramThreads);
-  const bool full = full_rows(np, n, V, ldv, q0, ldq);
-#define RCQR_GRAM(NPV)                                                                                                          \
-  if (full && q0)                                                                                                               \
-    hipLaunchKernelGGL((trsm_gram_kernel<NPV, true, true>), grid, block, 0, s, V, m, n, ldv, r0pk, info, gpart, q0, ldq);      \
-  else if (full)                                                                                                                \
-    hipLaunchKernelGGL((trsm_gram_kernel<NPV, true, false>), grid, block, 0, s, V, m, n, ldv, r0pk, info, gpart, q0, ldq);     \
-  else if (q0)                                                                                                                  \
-    hipLaunchKernelGGL((trsm_gram_kernel<NPV, false, true>), grid, block, 0, s, V, m, n, ldv, r0pk, info, gpart, q0, ldq);     \
-  else                                                                                                                          \
-    hipLaunchKernelGGL((trsm_gram_kernel<NPV, false, false>), grid, block, 0, s, V, m, n, ldv, r0pk, info, gpart, q0, ldq);
+                            double* gpart, double* q0, int64_t ldq, hipStream_t s, const MemberStride& ms) {
+  if (ms.count < 1) return hipErrorInvalidValue;
+  const dim3 grid(kGramBlocks, ms.count), block(kGramThreads);
+  const bool full = full_rows(np, n, V, ldv, q0, ldq) && ms.v % 2 == 0 && ms.q % 2 == 0;
+#define RCQR_GRAM_B(NPV, B)                                                                                                       \
+  if (full && q0)                                                                                                                 \
+    hipLaunchKernelGGL((trsm_gram_kernel<NPV, true, true, B>), grid, block, 0, s, V, m, n, ldv, r0pk, info, gpart, q0, ldq, ms);   \
+  else if (full)                                                                                                                  \
+    hipLaunchKernelGGL((trsm_gram_kernel<NPV, true, false, B>), grid, block, 0, s, V, m, n, ldv, r0pk, info, gpart, q0, ldq, ms);  \
+  else if (q0)                                                                                                                    \
+    hipLaunchKernelGGL((trsm_gram_kernel<NPV, false, true, B>), grid, block, 0, s, V, m, n, ldv, r0pk, info, gpart, q0, ldq, ms);  \
+  else                                                                                                                            \
+    hipLaunchKernelGGL((trsm_gram_kernel<NPV, false, false, B>), grid, block, 0, s, V, m, n, ldv, r0pk, info, gpart, q0, ldq, ms);
+#define RCQR_GRAM(NPV)       \
+  if (ms.count > 1) {        \
+    RCQR_GRAM_B(NPV, true)   \
+  } else {                   \
+    RCQR_GRAM_B(NPV, false)  \
+  }
   switch (np) {
     case 16: RCQR_GRAM(16) break;
     case 32: RCQR_GRAM(32) break;
@@ -489,6 +514,7 @@ hipError_t launch_trsm_gram(int np, const double* V, int64_t m, int n, int64_t l
     default: return hipErrorInvalidValue;
   }
 #undef RCQR_GRAM
+#undef RCQR_GRAM_B
   return hipGetLastError();
 }
 
@@ -508,21 +534,29 @@ hipError_t prepare_stream_launches() {
 }
 
 hipError_t launch_final(int np, bool apply_r1, const double* V, int64_t m, int n, int64_t ldv, const double* r0pk,
-                        const double* r1pk, const int32_t* info, double* Q, int64_t ldq, hipStream_t s, int grid_mult) {
+                        const double* r1pk, const int32_t* info, double* Q, int64_t ldq, hipStream_t s, int grid_mult,
+                        const MemberStride& ms) {
   if (m <= 0) return hipSuccess;
-  const bool full = full_rows(np, n, V, ldv, Q, ldq);
+  if (ms.count < 1 || (!apply_r1 && ms.count != 1)) return hipErrorInvalidValue;  // batches: the two-factor pass only
+  const bool full = full_rows(np, n, V, ldv, Q, ldq) && ms.v % 2 == 0 && ms.q % 2 == 0;
   const int64_t tiles = (m + kWave - 1) / kWave;
   if (apply_r1) {
     // eight waves per workgroup, about two workgroups per CU over the whole pass
     constexpr int NW = 8;
     int64_t g = (tiles + NW - 1) / NW;
     if (g > (int64_t)grid_mult * final_grid()) g = (int64_t)grid_mult * final_grid();
-    const dim3 grid((unsigned)g), block(NW * kWave);
-#define RCQR_FINAL_MFMA(NPV)                                                                                                  \
-  if (full)                                                                                                                   \
-    hipLaunchKernelGGL((final_mfma_kernel<NPV, true, NW>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq);      \
-  else                                                                                                                        \
-    hipLaunchKernelGGL((final_mfma_kernel<NPV, false, NW>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq);
+    const dim3 grid((unsigned)g, ms.count), block(NW * kWave);
+#define RCQR_FINAL_MFMA_B(NPV, B)                                                                                               \
+  if (full)                                                                                                                     \
+    hipLaunchKernelGGL((final_mfma_kernel<NPV, true, NW, B>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq, ms);  \
+  else                                                                                                                          \
+    hipLaunchKernelGGL((final_mfma_kernel<NPV, false, NW, B>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq, ms);
+#define RCQR_FINAL_MFMA(NPV)       \
+  if (ms.count > 1) {              \
+    RCQR_FINAL_MFMA_B(NPV, true)   \
+  } else {                         \
+    RCQR_FINAL_MFMA_B(NPV, false)  \
+  }
     switch (np) {
       case 16: RCQR_FINAL_MFMA(16) break;
       case 32: RCQR_FINAL_MFMA(32) break;
@@ -530,6 +564,7 @@ hipError_t launch_final(int np, bool apply_r1, const double* V, int64_t m, int n
       default: return hipErrorInvalidValue;
     }
 #undef RCQR_FINAL_MFMA
+#undef RCQR_FINAL_MFMA_B
     return hipGetLastError();
   }
   // one factor: Q0 = V R0^{-1} only (persistent, one workgroup per CU)

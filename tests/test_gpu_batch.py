@@ -75,3 +75,49 @@ def test_batch_refuses_a_repeated_plan():
     for p in plans:
         p.close()
     torch.cuda.synchronize()
+
+
+# rcqr_factor_batch: same-shaped members in one set of launches (LDS and bucket-index
+# CountSketch, 8 to 64 columns, ragged m)
+@pytest.mark.parametrize("m,n,s1,s2", [(10_000, 16, 512, 64), (5000, 8, 128, 32), (20_001, 50, 5000, 200), (30_000, 64, 8192, 256),
+                                       (3001, 32, 2048, 128)])
+def test_factor_batch_matches_single_calls(m, n, s1, s2):
+    print("factor_batch:", m, n, s1, s2, flush=True)
+    k, seed = 5, 80
+    V = torch.stack([torch.from_numpy(synth.make_V(m, n, 1e8, seed=seed + b)) for b in range(k)]).to("cuda")
+    V[2, :, n // 2] = 0.0  # member 2 is rank deficient: its sketch has a zero pivot
+    with rc.Plan(m, n, s1, s2, seed=seed, batch=k + 2) as pb:
+        Q, R = pb.factor_batch(V)
+        torch.cuda.synchronize()
+        st = [pb.info_member(b) for b in range(k)]
+        # a smaller batch on the same plan, in place (Q is V)
+        Vi = V[:3].clone()
+        Qi, Ri = pb.factor_batch(Vi, Q=Vi)
+        torch.cuda.synchronize()
+        st_i = [pb.info_member(b) for b in range(3)]
+    for b in range(k):
+        with rc.Plan(m, n, s1, s2, seed=seed + b) as p:
+            Qs, Rs = p.factor(V[b], check=False)
+            torch.cuda.synchronize()
+            assert st[b] == p.info(), b
+        if b == 2:
+            assert st[b][0] == rc.E_RANK
+            continue
+        assert st[b] == (rc.OK, 0)
+        assert torch.equal(Q[b], Qs) and torch.equal(R[b], Rs), b
+        if b < 3:
+            assert st_i[b] == st[b]
+            assert torch.equal(Qi[b], Qs) and torch.equal(Ri[b], Rs), b
+    torch.cuda.synchronize()
+
+
+def test_factor_batch_limits():
+    with rc.Plan(1000, 16, 512, 64, seed=1, batch=2) as p:
+        V = torch.zeros((3, 1000, 16), dtype=torch.float64, device="cuda")
+        with pytest.raises(rc.RcqrError):
+            p.factor_batch(V)  # more members than the workspace holds
+    with rc.Plan(1000, 100, 2000, 200, seed=1, batch=2) as p:
+        V = torch.zeros((2, 1000, 100), dtype=torch.float64, device="cuda")
+        with pytest.raises(rc.RcqrError):
+            p.factor_batch(V)  # more than 64 columns
+    torch.cuda.synchronize()
