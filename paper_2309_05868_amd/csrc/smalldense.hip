@@ -19,46 +19,50 @@ namespace rcqr {
 
 // ------------------------------------------------------------------------------------------
 // Householder QR of a p x n block (p <= 256, n <= 128), R factor only, matrix in registers.
-// Sixteen waves; wave w owns columns w, w + 16, ... (NC of them) and lane l owns rows l, l + 64,
-// l + 128, l + 192, so every column reduction is one wave's butterfly.  Reflector j is built by
-// the owner of column j: it maps x = A[j:, j] to beta e1, beta = -sign(x0) ||x||,
-// H = I - tau v v^T with v[0] = 1; v and tau go through LDS (double-buffered, so one workgroup
-// barrier per reflector) and every wave applies H to its columns right of j.  Look-ahead: the
-// owner of column j + 1 applies H_j to that column first and publishes reflector j + 1 before
-// updating its other columns, at raised wave priority, so the serial chain per reflector is one
-// column update, one norm and the reflector (the order of every column's operations is unchanged).
+// Sixteen waves; lane l owns rows l, l + 64, l + 128, l + 192, so every column reduction is one
+// wave's butterfly.  Reflector j maps x = A[j:, j] to beta e1, beta = -sign(x0) ||x||,
+// H = I - tau v v^T with v[0] = 1.  Reflectors are made two at a time: wave w owns the column
+// pairs (2w, 2w + 1), (2w + 32, 2w + 33), ...; the owner of pair (j, j + 1) builds H_j, applies it
+// to column j + 1 and builds H_{j+1}, and both go through LDS (double-buffered) behind one
+// workgroup barrier, after which every wave applies H_j and then H_{j+1} to its columns right of
+// j + 1.  Look-ahead: the owner of the next pair updates that pair first and publishes its two
+// reflectors before its other columns, at raised wave priority.  Every column still receives
+// H_0, H_1, ... in order through the same operations, so the factor is the same as with one
+// reflector per barrier; only the number of barriers halves.
 // ------------------------------------------------------------------------------------------
 constexpr int kQrMaxRows = 256;
 constexpr int kQrWaves = 16;
-
 
 template <int NC, class T>
 __global__ __launch_bounds__(kQrWaves * kWave) void qr_block_kernel(const T* __restrict__ in, int64_t ldin, int64_t p_total,
                                                                     int64_t rows_per_block, int n, T* __restrict__ out,
                                                                     int64_t member_bytes) {
+  static_assert(NC % 2 == 0, "columns are owned in pairs");
   constexpr int ER = kQrMaxRows / kWave;  // rows per lane
   in = member_ptr(in, (int64_t)blockIdx.y * member_bytes);  // batch member
   out = member_ptr(out, (int64_t)blockIdx.y * member_bytes);
-  __shared__ T vbuf[2][kQrMaxRows];
-  __shared__ T taub[2];
+  __shared__ T vbuf[2][2][kQrMaxRows];  // [pair parity][first / second reflector of the pair]
+  __shared__ T taub[2][2];
   const int wave = threadIdx.x / kWave, lane = lane_id();
   const int64_t r_beg = (int64_t)blockIdx.x * rows_per_block;
   const int64_t p64 = p_total - r_beg < rows_per_block ? p_total - r_beg : rows_per_block;
   const int p = (int)p64;
   const T* A0 = in + r_beg * ldin;
+  // slot q of wave w holds column 32 (q / 2) + 2 w + (q % 2)
+  auto col_of = [&](int q) { return 32 * (q / 2) + 2 * wave + (q % 2); };
   T a[NC][ER];
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
-    const int c = wave + kQrWaves * q;
+    const int c = col_of(q);
 #pragma unroll
     for (int e = 0; e < ER; ++e) {
       const int r = lane + kWave * e;
       a[q][e] = (r < p && c < n) ? A0[(int64_t)r * ldin + c] : T(0);
     }
   }
-  // Reflector j from the owner's (fully updated) column j, into buffer j & 1.
-  auto make_reflector = [&](int j) {
-    const int oq = j / kQrWaves, buf = j & 1;
+  // Reflector j from the owner's (fully updated) column j, in slot oq: into vbuf[buf][half] /
+  // taub[buf][half] and into v (this lane's entries), tau.
+  auto make_reflector = [&](int j, int oq, int buf, int half, T (&v)[ER], T& tau_out) {
     T x[ER];
 #pragma unroll
     for (int e = 0; e < ER; ++e) x[e] = T(0);
@@ -88,7 +92,8 @@ __global__ __launch_bounds__(kQrWaves * kWave) void qr_block_kernel(const T* __r
 #pragma unroll
     for (int e = 0; e < ER; ++e) {
       const int r = lane + kWave * e;
-      vbuf[buf][r] = (r == j) ? T(1) : (r > j ? x[e] * scal : T(0));
+      v[e] = (r == j) ? T(1) : (r > j ? x[e] * scal : T(0));
+      vbuf[buf][half][r] = v[e];
       x[e] = (r == j) ? beta : (r > j ? T(0) : x[e]);
     }
 #pragma unroll
@@ -97,12 +102,12 @@ __global__ __launch_bounds__(kQrWaves * kWave) void qr_block_kernel(const T* __r
 #pragma unroll
         for (int e = 0; e < ER; ++e) a[q][e] = x[e];
       }
-    if (lane == 0) taub[buf] = tau;
+    if (lane == 0) taub[buf][half] = tau;
+    tau_out = tau;
   };
-  // H_j applied to the wave's column q (when it lies right of j): a -= tau (v . a) v
-  auto apply = [&](int q, int j, T tau, const T (&v)[ER]) {
-    const int c = wave + kQrWaves * q;
-    if (c > j && c < n) {
+  // H applied to the wave's slot q: a -= tau (v . a) v
+  auto apply = [&](int q, T tau, const T (&v)[ER]) {
+    if (tau != T(0)) {
       T d = T(0);
 #pragma unroll
       for (int e = 0; e < ER; ++e) d = fma_t(v[e], a[q][e], d);
@@ -113,40 +118,62 @@ __global__ __launch_bounds__(kQrWaves * kWave) void qr_block_kernel(const T* __r
     }
   };
   const int steps = n < p ? n : p;
-  if (steps > 0 && wave == 0) make_reflector(0);
-  for (int j = 0; j < steps; ++j) {
-    __syncthreads();  // reflector j published; every read of reflector j - 1 is done
-    const T tau = taub[j & 1];
-    T v[ER];
+  const int npairs = (steps + 1) / 2;
+  // Pair pp, made by its owner (wave pp % 16, slots 2 (pp / 16) and 2 (pp / 16) + 1).
+  auto make_pair = [&](int pp) {
+    const int j = 2 * pp, q0 = 2 * (pp / kQrWaves), buf = pp & 1;
+    T v0[ER], tau0;
+    make_reflector(j, q0, buf, 0, v0, tau0);
+    if (j + 1 < steps) {
 #pragma unroll
-    for (int e = 0; e < ER; ++e) v[e] = vbuf[j & 1][lane + kWave * e];
-    const int nxt = j + 1;
-    if (nxt < steps && wave == nxt % kQrWaves) {
-      // look-ahead: this wave owns column j + 1, the only work on the path to the next
-      // barrier; it runs at raised priority, its other columns afterwards
-      const int nq = nxt / kQrWaves;
+      for (int q = 0; q < NC; ++q)
+        if (q == q0 + 1) apply(q, tau0, v0);
+      T v1[ER], tau1;
+      make_reflector(j + 1, q0 + 1, buf, 1, v1, tau1);
+    } else if (lane == 0) {
+      taub[buf][1] = T(0);  // odd number of steps: the pair has one reflector
+    }
+  };
+  if (npairs > 0 && wave == 0) make_pair(0);
+  for (int pp = 0; pp < npairs; ++pp) {
+    __syncthreads();  // pair pp published; every read of pair pp - 1 is done
+    const int j = 2 * pp, buf = pp & 1;
+    const T tau0 = taub[buf][0], tau1 = taub[buf][1];
+    T v0[ER], v1[ER];
+#pragma unroll
+    for (int e = 0; e < ER; ++e) {
+      v0[e] = vbuf[buf][0][lane + kWave * e];
+      v1[e] = vbuf[buf][1][lane + kWave * e];
+    }
+    // columns right of j + 1 take H_j, then H_{j+1}
+    auto update = [&](int q) {
+      const int c = col_of(q);
+      if (c > j + 1 && c < n) {
+        apply(q, tau0, v0);
+        apply(q, tau1, v1);
+      }
+    };
+    const int nxt = pp + 1;
+    if (nxt < npairs && wave == nxt % kQrWaves) {
+      const int nq = 2 * (nxt / kQrWaves);
       __builtin_amdgcn_s_setprio(3);
-      if (tau != T(0)) {
 #pragma unroll
-        for (int q = 0; q < NC; ++q)
-          if (q == nq) apply(q, j, tau, v);
-      }
-      make_reflector(nxt);
+      for (int q = 0; q < NC; ++q)
+        if (q == nq || q == nq + 1) update(q);
+      make_pair(nxt);
       __builtin_amdgcn_s_setprio(0);
-      if (tau != T(0)) {
 #pragma unroll
-        for (int q = 0; q < NC; ++q)
-          if (q != nq) apply(q, j, tau, v);
-      }
-    } else if (tau != T(0)) {
+      for (int q = 0; q < NC; ++q)
+        if (q != nq && q != nq + 1) update(q);
+    } else {
 #pragma unroll
-      for (int q = 0; q < NC; ++q) apply(q, j, tau, v);
+      for (int q = 0; q < NC; ++q) update(q);
     }
   }
   T* R = out + (int64_t)blockIdx.x * n * n;
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
-    const int c = wave + kQrWaves * q;
+    const int c = col_of(q);
 #pragma unroll
     for (int e = 0; e < ER; ++e) {
       const int r = lane + kWave * e;
@@ -161,9 +188,7 @@ static hipError_t qr_blocks_any(const T* in, int64_t ldin, int64_t p_total, int6
   if (rows_per_block > kQrMaxRows || n > RCQR_MAX_N || n < 1 || ms.count < 1) return hipErrorInvalidValue;
   const dim3 grid((unsigned)nblocks, ms.count), block(kQrWaves * kWave);
   const int64_t mbytes = ms.ws;
-  if (n <= 16)
-    hipLaunchKernelGGL((qr_block_kernel<1, T>), grid, block, 0, s, in, ldin, p_total, rows_per_block, n, out, mbytes);
-  else if (n <= 32)
+  if (n <= 32)
     hipLaunchKernelGGL((qr_block_kernel<2, T>), grid, block, 0, s, in, ldin, p_total, rows_per_block, n, out, mbytes);
   else if (n <= 64)
     hipLaunchKernelGGL((qr_block_kernel<4, T>), grid, block, 0, s, in, ldin, p_total, rows_per_block, n, out, mbytes);
