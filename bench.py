@@ -267,6 +267,57 @@ def serve_workload(args):
     print(json.dumps(line), flush=True)
 
 
+SERVE_SMALL = dict(count=4096, rate_per_s=200_000.0, m=10_000, n=16, s1=512, s2=64, bank=16, seed=12)
+
+
+def serve_small_workload(args):
+    """Serving many small same-shaped requests (the small configuration's shape, kappa log-uniform
+    in [1e2, 1e12]) arriving faster than one-at-a-time service: one at a time, continuous
+    batching over streams, and continuous batching that also groups same-shaped requests into
+    rcqr_factor_batch launches (up to 64 per launch).  QR/s and p50 / p99 latency."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2309_05868_amd import serve as srv
+
+    wl = SERVE_SMALL
+    dev = torch.device("cuda:0")
+    m, n = wl["m"], wl["n"]
+    rng = np.random.Generator(np.random.PCG64(wl["seed"]))
+    gaps = rng.exponential(1.0 / wl["rate_per_s"], size=wl["count"])
+    arrivals = np.cumsum(gaps) - gaps[0]
+    kap = np.exp(rng.uniform(np.log(1e2), np.log(1e12), size=wl["bank"]))
+    bank = [torch.from_numpy(synth.make_V(m, n, float(kap[i]), wl["seed"] + i)).to(dev) for i in range(wl["bank"])]
+    reqs = [{"arrival_s": float(arrivals[i]), "m": m, "n": n, "s1": wl["s1"], "s2": wl["s2"], "seed": 10_000 + i,
+             "kappa": float(kap[i % wl["bank"]]), "bank": i % wl["bank"]} for i in range(wl["count"])]
+
+    def get_V(r):
+        return bank[r["bank"]]
+
+    torch.cuda.synchronize()
+    srv.serve([dict(r, arrival_s=0.0) for r in reqs[:64]], get_V, slots=4, budget_bytes=args.serve_budget_gb << 30, max_batch=64)
+    out = {}
+    for name, slots, mb in (("one_at_a_time", 1, 1), ("streams", 4, 1), ("streams_and_batches", 4, 64)):
+        log(f"bench: serving {len(reqs)} small requests, {name}")
+        run, summary, _ = srv.serve(reqs, get_V, slots=slots, budget_bytes=args.serve_budget_gb << 30, max_batch=mb)
+        summary["slots"], summary["max_batch"] = slots, mb
+        summary["mean_batch"] = float(np.mean([r["batch"] for r in run["results"]]))
+        out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summary.items()}
+        log(f"bench: {name}: {summary.get('qr_per_s', 0):.0f} QR/s, p50 {summary.get('p50_ms', 0):.2f} ms, "
+            f"p99 {summary.get('p99_ms', 0):.2f} ms, mean batch {summary['mean_batch']:.1f}")
+    line = {
+        "metric": METRIC, "value": out["streams_and_batches"].get("qr_per_s"), "unit": "QR/s", "n_gpus": 1,
+        "steps": len(reqs), "warmup": 64, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"rand_cholQR serving: {wl['count']} requests {m} x {n} (s1 {wl['s1']}, s2 {wl['s2']}), "
+                               f"Poisson {wl['rate_per_s']:.0f}/s, kappa log-uniform [1e2, 1e12]"},
+        "p50_ms": out["streams_and_batches"].get("p50_ms"), "p99_ms": out["streams_and_batches"].get("p99_ms"), "modes": out,
+        "note": "V from a resident bank of 16 matrices; latency = device completion - arrival",
+    }
+    print(json.dumps(line), flush=True)
+
+
 # bandwidth sweep: about 1-2 GB of V per n, three condition numbers, s1 = 2 n^2, s2 = 4 n
 SWEEP_SHAPES = [(16_777_216, 8), (8_388_608, 32), (2_097_152, 128)]
 SWEEP_KAPPAS = [1e2, 1e8, 1e15]
@@ -504,7 +555,7 @@ def main():
     ap.add_argument("--tune", action="store_true", help="run rcqr_tune (result-neutral launch choices) before warm-up")
     ap.add_argument("--comparator-steps", type=int, default=5)
     ap.add_argument("--cpu-sample-rows", type=int, default=100_000)
-    ap.add_argument("--workload", choices=["default", "mixed", "serve", "latency", "sweep", "batch"], default="default",
+    ap.add_argument("--workload", choices=["default", "mixed", "serve", "serve_small", "latency", "sweep", "batch"], default="default",
                     help="mixed: FP32/BF16 preconditioner variants against FP64 at m=4e6, n=128, kappa=1e14; "
                          "serve: continuous batching of 4096 Poisson-arriving requests; "
                          "latency: small factorizations, eager vs HIP graph; sweep: n in {8, 32, 128} at 1-2 GB")
@@ -551,6 +602,9 @@ def main():
         return
     if args.workload == "batch":
         batch_workload(args)
+        return
+    if args.workload == "serve_small":
+        serve_small_workload(args)
         return
     wl = WORKLOAD
     m, n = wl["m"], wl["n"]

@@ -227,13 +227,14 @@ rcqr_status_t rcqr_batch_destroy(rcqr_batch_t batch);
 /*
  * Same-shaped batches in one set of launches.  rcqr_factor_batch() runs rcqr_factor (Algorithm 3)
  * on `count` matrices of the plan's shape at once: member b reads V + b * stride_v (leading
- * dimension ldv), writes Q + b * stride_q and R + b * stride_r, uses the sketch seed
- * (plan seed + b) and the b-th slice of the workspace, which must then hold
+ * dimension ldv), writes Q + b * stride_q and R + b * stride_r, uses the sketch seed d_seeds[b]
+ * (a device array of `count` seeds, read by the kernels; or, when d_seeds is null, the plan's
+ * seed + b) and the b-th slice of the workspace, which must then hold
  * count * rcqr_workspace_bytes(m, n, s1, s2, 0) bytes (the size given to rcqr_plan).  Each of
  * the eleven kernels of the factorization is launched once for the whole batch, the member
  * being a grid index, so a batch of small factorizations costs the launches of one and fills the
- * GPU with all of them.  Member b gives bitwise the Q and R of rcqr_factor on a plan with seed
- * (plan seed + b).  Supported for n <= 64, s2 <= 256, flags 0 and count <= 4096; otherwise
+ * GPU with all of them.  Member b gives bitwise the Q and R of rcqr_factor on a plan with its
+ * seed.  Supported for n <= 64, s2 <= 256, flags 0 and count <= 4096; otherwise
  * RCQR_E_UNSUPPORTED.
  * Strides must keep members apart (stride_v >= m * ldv, stride_q >= m * ldq, stride_r >= n * ldr;
  * Q may be V with the same leading dimension and stride); RCQR_E_INVALID otherwise, or when the
@@ -241,8 +242,12 @@ rcqr_status_t rcqr_batch_destroy(rcqr_batch_t batch);
  * (synchronises the plan's stream).  Timing (rcqr_set_timing) does not record batches.
  */
 rcqr_status_t rcqr_factor_batch(rcqr_plan_t plan, int32_t count, const double* d_V, int64_t ldv, int64_t stride_v,
-                                double* d_Q, int64_t ldq, int64_t stride_q, double* d_R, int64_t ldr, int64_t stride_r);
+                                double* d_Q, int64_t ldq, int64_t stride_q, double* d_R, int64_t ldr, int64_t stride_r,
+                                const uint64_t* d_seeds);
 rcqr_status_t rcqr_info_member(rcqr_plan_t plan, int32_t member, int32_t* status, int32_t* column);
+/* Statuses of members 0 .. count-1 into host arrays status[count], column[count] with one copy
+ * (synchronises the plan's stream).  RCQR_E_INVALID for count < 1 or beyond the workspace. */
+rcqr_status_t rcqr_info_batch(rcqr_plan_t plan, int32_t count, int32_t* status, int32_t* column);
 
 /* ------------------------------------------------------------------------------------------
  * Inspection entry points (same library; used by tests, never on a timed path).

@@ -55,8 +55,9 @@ _SIGNATURES = {
                                    ctypes.POINTER(_c_p), ctypes.POINTER(_c_i64), ctypes.POINTER(_c_p), ctypes.POINTER(_c_i64),
                                    ctypes.POINTER(_c_p)]),
     "rcqr_batch_launch": (_c_i32, [_c_p]),
-    "rcqr_factor_batch": (_c_i32, [_c_p, _c_i32, _c_p, _c_i64, _c_i64, _c_p, _c_i64, _c_i64, _c_p, _c_i64, _c_i64]),
+    "rcqr_factor_batch": (_c_i32, [_c_p, _c_i32, _c_p, _c_i64, _c_i64, _c_p, _c_i64, _c_i64, _c_p, _c_i64, _c_i64, _c_p]),
     "rcqr_info_member": (_c_i32, [_c_p, _c_i32, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32)]),
+    "rcqr_info_batch": (_c_i32, [_c_p, _c_i32, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32)]),
     "rcqr_batch_destroy": (_c_i32, [_c_p]),
 }
 
@@ -215,9 +216,10 @@ class Plan:
     def set_tuning(self, final_mode, grid_mult):
         _check(lib().rcqr_set_tuning(self._h, int(final_mode), int(grid_mult)), "rcqr_set_tuning")
 
-    def factor_batch(self, V, Q=None, R=None):
-        """rcqr_factor_batch: V of shape (count, m, n), count <= the plan's batch; member b uses the
-        seed (plan seed + b).  Returns (Q, R) of shapes (count, m, n) and (count, n, n)."""
+    def factor_batch(self, V, Q=None, R=None, seeds=None):
+        """rcqr_factor_batch: V of shape (count, m, n), count <= the plan's batch; member b uses
+        seeds[b] (a CUDA int64/uint64 tensor of count seeds) or, without seeds, the plan's seed + b.
+        Returns (Q, R) of shapes (count, m, n) and (count, n, n)."""
         if V.dim() != 3 or V.shape[1:] != (self.m, self.n) or V.dtype != torch.float64 or not V.is_cuda:
             raise ValueError("V must be a CUDA float64 tensor of shape (count, m, n)")
         k = V.shape[0]
@@ -228,10 +230,21 @@ class Plan:
         for t, nm in ((V, "V"), (Q, "Q"), (R, "R")):
             if t.stride(2) != 1:
                 raise ValueError(f"{nm} rows must be contiguous")
+        sp = None
+        if seeds is not None:
+            if not seeds.is_cuda or seeds.dtype not in (torch.int64, torch.uint64) or seeds.numel() < k or not seeds.is_contiguous():
+                raise ValueError("seeds must be a contiguous CUDA int64 tensor with one seed per member")
+            sp = ctypes.c_void_p(seeds.data_ptr())
         _check(lib().rcqr_factor_batch(self._h, k, ctypes.c_void_p(V.data_ptr()), V.stride(1), V.stride(0),
                                        ctypes.c_void_p(Q.data_ptr()), Q.stride(1), Q.stride(0),
-                                       ctypes.c_void_p(R.data_ptr()), R.stride(1), R.stride(0)), "rcqr_factor_batch")
+                                       ctypes.c_void_p(R.data_ptr()), R.stride(1), R.stride(0), sp), "rcqr_factor_batch")
         return Q, R
+
+    def info_batch(self, count):
+        """[(status, column)] of members 0 .. count-1, one device-to-host copy."""
+        st, col = (_c_i32 * int(count))(), (_c_i32 * int(count))()
+        _check(lib().rcqr_info_batch(self._h, int(count), st, col), "rcqr_info_batch")
+        return [(st[i], col[i]) for i in range(int(count))]
 
     def info_member(self, b):
         st, col = _c_i32(), _c_i32()

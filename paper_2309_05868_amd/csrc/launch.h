@@ -9,12 +9,18 @@ namespace rcqr {
 
 // A batch of same-shaped factorizations in one set of launches: member b of a launch is a grid
 // index (blockIdx.y, or blockIdx.z where y is taken); its workspace pointers move by b * ws
-// bytes, V, Q and R by b * v, b * q, b * r elements, and its sketch seed by b.  All zero, one
-// member, for a single factorization (the kernels then compute exactly what they did alone).
+// bytes, V, Q and R by b * v, b * q, b * r elements, and its sketch seed is seeds[b] (a device
+// array) or, without one, the plan's seed + b.  All zero, one member, for a single
+// factorization (the kernels then compute exactly what they did alone).
 struct MemberStride {
   int64_t ws = 0, v = 0, q = 0, r = 0;
   int32_t count = 1;
+  const uint64_t* seeds = nullptr;
 };
+
+__host__ __device__ inline uint64_t member_seed(uint64_t seed, const MemberStride& ms, int64_t b) {
+  return ms.seeds != nullptr ? ms.seeds[b] : seed + (uint64_t)b;
+}
 
 template <class T>
 __host__ __device__ inline T* member_ptr(T* p, int64_t bytes) {

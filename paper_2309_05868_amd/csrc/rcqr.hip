@@ -440,7 +440,7 @@ rcqr_status_t rcqr_factor(rcqr_plan_t p, const double* V, int64_t ldv, double* Q
 }
 
 rcqr_status_t rcqr_factor_batch(rcqr_plan_t p, int32_t count, const double* V, int64_t ldv, int64_t sv, double* Q, int64_t ldq,
-                                int64_t sq, double* R, int64_t ldr, int64_t sr) {
+                                int64_t sq, double* R, int64_t ldr, int64_t sr, const uint64_t* d_seeds) {
   const rcqr_status_t st = check_io(p, V, ldv, Q, ldq, R, ldr);
   if (st != RCQR_OK) return st;
   const Shape& sh = p->sh;
@@ -458,6 +458,7 @@ rcqr_status_t rcqr_factor_batch(rcqr_plan_t p, int32_t count, const double* V, i
   ms.q = sq;
   ms.r = sr;
   ms.count = count;
+  ms.seeds = d_seeds;
   int32_t* info = p->at<int32_t>(L.info);
   // the steps of rcqr_factor on the small-sketch FP64 path, each one launch for all members
   RCQR_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(info), 16, 0u, s, count, ms.ws / 4));
@@ -501,6 +502,25 @@ rcqr_status_t rcqr_info_member(rcqr_plan_t p, int32_t member, int32_t* status, i
   *status = h[0];
   *column = h[1];
   return RCQR_OK;
+}
+
+rcqr_status_t rcqr_info_batch(rcqr_plan_t p, int32_t count, int32_t* status, int32_t* column) {
+  if (p == nullptr || status == nullptr || column == nullptr || count < 1 || (size_t)count > p->ws_bytes / p->L.total)
+    return RCQR_E_INVALID;
+  int32_t* h = new (std::nothrow) int32_t[2 * (size_t)count];
+  if (h == nullptr) return RCQR_E_NOMEM;
+  // one strided copy: the first two words of every member's status block
+  const hipError_t e = hipMemcpy2DAsync(h, 2 * sizeof(int32_t), p->ws + p->L.info, p->L.total, 2 * sizeof(int32_t), (size_t)count,
+                                        hipMemcpyDeviceToHost, p->stream);
+  const hipError_t e2 = e == hipSuccess ? hipStreamSynchronize(p->stream) : e;
+  if (e2 == hipSuccess) {
+    for (int32_t b = 0; b < count; ++b) {
+      status[b] = h[2 * b];
+      column[b] = h[2 * b + 1];
+    }
+  }
+  delete[] h;
+  return e2 == hipSuccess ? RCQR_OK : RCQR_E_HIP;
 }
 
 rcqr_status_t rcqr_cholqr2(rcqr_plan_t p, const double* V, int64_t ldv, double* Q, int64_t ldq, double* R, int64_t ldr) {

@@ -55,13 +55,13 @@ constexpr int kHistLds = 16384;  // buckets counted in LDS; above this, in the c
 int64_t bucket_chunk_rows(int64_t m, int nchunk) { return ((m + nchunk - 1) / nchunk + 3) / 4 * 4; }
 
 __global__ __launch_bounds__(256) void hash_hist_kernel(int64_t m, uint64_t s1, uint64_t seed, int64_t chunk_rows, uint32_t* __restrict__ codes,
-                                                        uint32_t* __restrict__ hist, int64_t member_bytes) {
+                                                        uint32_t* __restrict__ hist, MemberStride ms) {
   __shared__ uint32_t lh[kHistLds];
   {
     const int64_t mb = blockIdx.y;  // batch member
-    codes = member_ptr(codes, mb * member_bytes);
-    hist = member_ptr(hist, mb * member_bytes);
-    seed += (uint64_t)mb;
+    codes = member_ptr(codes, mb * ms.ws);
+    hist = member_ptr(hist, mb * ms.ws);
+    seed = member_seed(seed, ms, mb);
   }
   const bool in_lds = s1 <= (uint64_t)kHistLds;
   uint32_t* gh = hist + (int64_t)blockIdx.x * (int64_t)s1;
@@ -100,7 +100,7 @@ hipError_t launch_hash_hist(int64_t m, int64_t s1, uint64_t seed, int nchunk, ui
   if (m <= 0) return hipSuccess;
   if (ms.count < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(hash_hist_kernel, dim3(nchunk, ms.count), dim3(256), 0, s, m, (uint64_t)s1, seed, bucket_chunk_rows(m, nchunk), codes,
-                     hist, ms.ws);
+                     hist, ms);
   return hipGetLastError();
 }
 
@@ -586,7 +586,7 @@ __global__ __launch_bounds__(256) void countsketch_lds_kernel(const double* __re
     const int64_t mb = blockIdx.y;  // batch member
     V += mb * ms.v;
     parts = member_ptr(parts, mb * ms.ws);
-    seed += (uint64_t)mb;
+    seed = member_seed(seed, ms, mb);
   }
   __shared__ uint32_t codes[4][kCsChunk];
   constexpr int RB = kWave / NPL;  // rows per batch
@@ -820,7 +820,7 @@ __global__ __launch_bounds__(256) void gauss_mfma64_kernel(const double* __restr
     const int64_t mb = blockIdx.z;  // batch member
     W1 = member_ptr(W1, mb * ms.ws);
     wpart = member_ptr(wpart, mb * ms.ws);
-    seed += (uint64_t)mb;
+    seed = member_seed(seed, ms, mb);
   }
   __shared__ double st[kGemmRows][kMmK + 1];  // S2 tile, [row j][k]
   __shared__ double wt[NP][kMmK + 1];         // W1 tile transposed, [column c][k]

@@ -8,6 +8,12 @@ device: one request's single-workgroup steps (Householder of the sketch, Cholesk
 other compute units to the streaming passes of the others.  Completions are found by polling HIP
 events; a request's latency is its device completion time minus its arrival time.
 
+With max_batch > 1 the loop also batches: when the head request is admitted, requests behind it
+that have already arrived and have the same shape (backend.shape_key) join it, in arrival order,
+up to max_batch and within the memory budget, and run as one rcqr_factor_batch launch on the
+slot (each with its own seed; results bitwise those of separate calls).  Same-shaped requests can
+thereby start ahead of earlier requests of other shapes; the head itself never waits.
+
 The scheduling logic is independent of the GPU (`Scheduler` with a backend); `GpuBackend` runs
 the factorizations through the C ABI, `serve()` wires the two together.
 """
@@ -25,15 +31,40 @@ class Scheduler:
 
     backend.footprint(req) -> bytes; backend.launch(req, slot) -> handle;
     backend.poll(handle) -> None while running, else (end_time_s, status).
+    With max_batch > 1 also backend.shape_key(req) (None: never batched) and
+    backend.launch_batch(reqs, slot) -> handle, whose poll gives (end_time_s, [status per request]).
     Times are seconds since the start of the run (backend.now() gives the current one).
     """
 
-    def __init__(self, backend, slots, budget_bytes):
-        if slots < 1 or budget_bytes <= 0:
-            raise ValueError("need at least one slot and a positive memory budget")
+    def __init__(self, backend, slots, budget_bytes, max_batch=1):
+        if slots < 1 or budget_bytes <= 0 or max_batch < 1:
+            raise ValueError("need at least one slot, a positive memory budget and max_batch >= 1")
         self.backend, self.slots, self.budget = backend, int(slots), int(budget_bytes)
+        self.max_batch = int(max_batch)
+
+    def _followers(self, pending, head, now, room):
+        """Arrived requests behind the head with its shape, in arrival order, that fit `room`."""
+        if self.max_batch == 1:
+            return []
+        key = self.backend.shape_key(head)
+        if key is None:
+            return []
+        out = []
+        for idx in list(pending)[1:]:
+            if len(out) + 1 >= self.max_batch:
+                break
+            req = self.requests[idx]
+            if req["arrival_s"] > now:
+                break
+            if self.backend.shape_key(req) == key:
+                fp = self.backend.footprint(req)
+                if fp <= room:
+                    out.append(idx)
+                    room -= fp
+        return out
 
     def run(self, requests, idle_sleep_s=0.0):
+        self.requests = requests
         order = sorted(range(len(requests)), key=lambda i: requests[i]["arrival_s"])
         pending = collections.deque(order)
         free_slots = list(range(self.slots))[::-1]
@@ -43,15 +74,18 @@ class Scheduler:
         results = [None] * len(requests)
         while pending or inflight:
             progressed = False
-            for idx in list(inflight):
-                slot, handle, fp, start = inflight[idx]
+            for key in list(inflight):
+                slot, handle, fp, start, members = inflight[key]
                 done = self.backend.poll(handle)
                 if done is not None:
                     end, status = done
-                    req = requests[idx]
-                    results[idx] = {"index": idx, "arrival_s": req["arrival_s"], "start_s": start, "end_s": end,
-                                    "latency_s": end - req["arrival_s"], "status": status, "slot": slot}
-                    del inflight[idx]
+                    statuses = status if isinstance(status, list) else [status]
+                    for idx, st in zip(members, statuses):
+                        req = requests[idx]
+                        results[idx] = {"index": idx, "arrival_s": req["arrival_s"], "start_s": start, "end_s": end,
+                                        "latency_s": end - req["arrival_s"], "status": st, "slot": slot,
+                                        "batch": len(members)}
+                    del inflight[key]
                     free_slots.append(slot)
                     used -= fp
                     progressed = True
@@ -73,11 +107,20 @@ class Scheduler:
                     break  # wait for memory; keep arrival order
                 pending.popleft()
                 slot = free_slots.pop()
-                handle = self.backend.launch(req, slot)
-                inflight[idx] = (slot, handle, fp, now)
+                group = self._followers(collections.deque([idx]) + pending, req, now, self.budget - used - fp)
+                if group:
+                    for g in group:
+                        pending.remove(g)
+                    members = [idx] + group
+                    fp += sum(self.backend.footprint(requests[g]) for g in group)
+                    handle = self.backend.launch_batch([requests[i] for i in members], slot)
+                else:
+                    members = [idx]
+                    handle = self.backend.launch(req, slot)
+                inflight[idx] = (slot, handle, fp, now, members)
                 used += fp
                 peak_used = max(peak_used, used)
-                peak_inflight = max(peak_inflight, len(inflight))
+                peak_inflight = max(peak_inflight, sum(len(v[4]) for v in inflight.values()))
                 progressed = True
             if not progressed and idle_sleep_s > 0:
                 time.sleep(idle_sleep_s)
@@ -87,8 +130,10 @@ class Scheduler:
 class GpuBackend:
     """Runs each request as one rcqr_factor on a slot's stream; V comes from get_V(req)."""
 
-    def __init__(self, get_V, slots, device="cuda:0", flags=0, keep_outputs=False):
+    def __init__(self, get_V, slots, device="cuda:0", flags=0, keep_outputs=False, batch_hint=1):
         self.device = torch.device(device)
+        self.batch_plans = {}
+        self.batch_hint = int(batch_hint)
         self.get_V = get_V
         self.flags = flags
         self.keep = keep_outputs
@@ -120,10 +165,53 @@ class GpuBackend:
             done.record(stream)
         return {"req": req, "plan": plan, "Q": Q, "R": R, "event": done}
 
+    def close(self):
+        for p in self.batch_plans.values():
+            p.close()
+        self.batch_plans = {}
+
+    def shape_key(self, req):
+        """Requests with equal keys can share one rcqr_factor_batch launch (n <= 64, s2 <= 256, FP64)."""
+        if self.flags != 0 or req["n"] > 64 or req["s2"] > 256:
+            return None
+        return (req["m"], req["n"], req["s1"], req["s2"])
+
+    def _batch_plan(self, slot, key, count):
+        """A batch plan per (slot, shape), reused while its workspace holds `count` members (a slot
+        runs one launch at a time, so its plans are free again once the launch is polled done)."""
+        cached = self.batch_plans.get((slot, key))
+        if cached is None or cached.batch < count:
+            if cached is not None:
+                cached.close()
+            m, n, s1, s2 = key
+            cached = Plan(m, n, s1, s2, 0, device=self.device, stream=self.streams[slot], batch=max(count, self.batch_hint))
+            self.batch_plans[(slot, key)] = cached
+        return cached
+
+    def launch_batch(self, reqs, slot):
+        stream = self.streams[slot]
+        key = self.shape_key(reqs[0])
+        k = len(reqs)
+        with torch.cuda.stream(stream):
+            Vb = torch.stack([self.get_V(r) for r in reqs])
+            host = torch.tensor([r["seed"] for r in reqs], dtype=torch.int64).pin_memory()
+            seeds = host.to(self.device, non_blocking=True)
+            plan = self._batch_plan(slot, key, k)
+            Q, R = plan.factor_batch(Vb, seeds=seeds)
+            done = torch.cuda.Event(enable_timing=True)
+            done.record(stream)
+        return {"reqs": reqs, "plan": plan, "Q": Q, "R": R, "event": done, "keep": (Vb, seeds, host)}
+
     def poll(self, handle):
         if not handle["event"].query():
             return None
         end = self.t0_event.elapsed_time(handle["event"]) * 1e-3
+        if "reqs" in handle:  # a batch (its plan stays cached for the slot)
+            sts = [st for st, _ in handle["plan"].info_batch(len(handle["reqs"]))]
+            if self.keep:
+                for b, r in enumerate(handle["reqs"]):
+                    self.outputs[r["seed"]] = (handle["Q"][b], handle["R"][b])
+            return end, sts
         st, _ = handle["plan"].info()
         if self.keep:
             self.outputs[handle["req"]["seed"]] = (handle["Q"], handle["R"])
@@ -149,9 +237,10 @@ def latency_summary(run):
             "peak_bytes": run["peak_bytes"], "peak_inflight": run["peak_inflight"]}
 
 
-def serve(requests, get_V, slots=4, budget_bytes=32 << 30, device="cuda:0", flags=0, keep_outputs=False):
+def serve(requests, get_V, slots=4, budget_bytes=32 << 30, device="cuda:0", flags=0, keep_outputs=False, max_batch=1):
     """Run the request list with continuous batching; returns (run, summary, backend)."""
-    backend = GpuBackend(get_V, slots, device=device, flags=flags, keep_outputs=keep_outputs)
-    run = Scheduler(backend, slots, budget_bytes).run(requests)
+    backend = GpuBackend(get_V, slots, device=device, flags=flags, keep_outputs=keep_outputs, batch_hint=max_batch)
+    run = Scheduler(backend, slots, budget_bytes, max_batch=max_batch).run(requests)
     torch.cuda.synchronize(backend.device)
+    backend.close()
     return run, latency_summary(run), backend

@@ -130,11 +130,11 @@ def test_plan_rejects_bad_arguments_on_host(lib):
     assert lib.rcqr_plan(ctypes.byref(h), m, n, 512, 64, 0, 0, ctypes.c_void_p(1 << 20), 2 * ws1, None) == rc.OK
     try:
         V, Q, R = ctypes.c_void_p(1 << 30), ctypes.c_void_p(1 << 31), ctypes.c_void_p(1 << 32)
-        assert lib.rcqr_factor_batch(h, 3, V, n, m * n, Q, n, m * n, R, n, n * n) == rc.E_INVALID      # 3 > workspace for 2
-        assert lib.rcqr_factor_batch(h, 0, V, n, m * n, Q, n, m * n, R, n, n * n) == rc.E_INVALID      # count < 1
-        assert lib.rcqr_factor_batch(h, 2, V, n, m * n - 1, Q, n, m * n, R, n, n * n) == rc.E_INVALID  # members overlap
-        assert lib.rcqr_factor_batch(h, 2, V, n, m * n, V, n, 2 * m * n, R, n, n * n) == rc.E_INVALID  # Q = V, other stride
-        assert lib.rcqr_factor_batch(None, 2, V, n, m * n, Q, n, m * n, R, n, n * n) == rc.E_INVALID
+        assert lib.rcqr_factor_batch(h, 3, V, n, m * n, Q, n, m * n, R, n, n * n, None) == rc.E_INVALID      # 3 > workspace for 2
+        assert lib.rcqr_factor_batch(h, 0, V, n, m * n, Q, n, m * n, R, n, n * n, None) == rc.E_INVALID      # count < 1
+        assert lib.rcqr_factor_batch(h, 2, V, n, m * n - 1, Q, n, m * n, R, n, n * n, None) == rc.E_INVALID  # members overlap
+        assert lib.rcqr_factor_batch(h, 2, V, n, m * n, V, n, 2 * m * n, R, n, n * n, None) == rc.E_INVALID  # Q = V, other stride
+        assert lib.rcqr_factor_batch(None, 2, V, n, m * n, Q, n, m * n, R, n, n * n, None) == rc.E_INVALID
         st, col = ctypes.c_int32(), ctypes.c_int32()
         assert lib.rcqr_info_member(h, 2, ctypes.byref(st), ctypes.byref(col)) == rc.E_INVALID        # no member 2
         assert lib.rcqr_info_member(h, -1, ctypes.byref(st), ctypes.byref(col)) == rc.E_INVALID
@@ -144,7 +144,7 @@ def test_plan_rejects_bad_arguments_on_host(lib):
     assert lib.rcqr_plan(ctypes.byref(h), m, 100, 2000, 200, 0, 0, ctypes.c_void_p(1 << 20), ws2, None) == rc.OK
     try:
         V, Q, R = ctypes.c_void_p(1 << 30), ctypes.c_void_p(1 << 31), ctypes.c_void_p(1 << 32)
-        assert lib.rcqr_factor_batch(h, 1, V, 100, m * 100, Q, 100, m * 100, R, 100, 100 * 100) == rc.E_UNSUPPORTED  # n > 64
+        assert lib.rcqr_factor_batch(h, 1, V, 100, m * 100, Q, 100, m * 100, R, 100, 100 * 100, None) == rc.E_UNSUPPORTED  # n > 64
     finally:
         assert lib.rcqr_destroy(h) == rc.OK
 

@@ -90,11 +90,24 @@ def test_factor_batch_matches_single_calls(m, n, s1, s2):
         Q, R = pb.factor_batch(V)
         torch.cuda.synchronize()
         st = [pb.info_member(b) for b in range(k)]
+        assert pb.info_batch(k) == st
         # a smaller batch on the same plan, in place (Q is V)
         Vi = V[:3].clone()
         Qi, Ri = pb.factor_batch(Vi, Q=Vi)
         torch.cuda.synchronize()
         st_i = [pb.info_member(b) for b in range(3)]
+    # explicit, non-consecutive seeds (a device array)
+    seeds = [900, 17, 4242, 5, 77][:k]
+    with rc.Plan(m, n, s1, s2, seed=0, batch=k) as pb:
+        Qx, Rx = pb.factor_batch(V, seeds=torch.tensor(seeds, dtype=torch.int64, device="cuda"))
+        torch.cuda.synchronize()
+        st_x = [pb.info_member(b) for b in range(k)]
+    for b in (0, 3):
+        with rc.Plan(m, n, s1, s2, seed=seeds[b]) as p:
+            Qs, Rs = p.factor(V[b])
+            torch.cuda.synchronize()
+        assert st_x[b] == (rc.OK, 0)
+        assert torch.equal(Qx[b], Qs) and torch.equal(Rx[b], Rs), ("seeds", b)
     for b in range(k):
         with rc.Plan(m, n, s1, s2, seed=seed + b) as p:
             Qs, Rs = p.factor(V[b], check=False)

@@ -54,3 +54,26 @@ def test_memory_budget_serialises_requests():
     run, summary, _ = srv.serve(reqs, lambda r: Vs[r["seed"]], slots=4, budget_bytes=one)
     assert summary["completed"] == 6 and summary["ok"] == 6
     assert run["peak_inflight"] == 1 and run["peak_bytes"] <= one
+
+
+def test_same_shape_requests_batched_equal_solo_results():
+    # 40 requests of three shapes arriving together: the loop groups same-shaped ones into
+    # rcqr_factor_batch launches (per-request seeds); each result is bitwise the solo result
+    shapes = [(10_000, 16, 512, 64), (5000, 8, 128, 32), (20_000, 64, 8192, 256)]
+    reqs = []
+    for i in range(40):
+        m, n, s1, s2 = shapes[i % 3]
+        reqs.append({"arrival_s": 0.0, "m": m, "n": n, "s1": s1, "s2": s2, "seed": 500 + 7 * i, "kappa": 1e6})
+    Vs = {r["seed"]: torch.from_numpy(synth.make_V(r["m"], r["n"], r["kappa"], r["seed"])).to("cuda") for r in reqs}
+    print("serving: 40 requests, batches of up to 8", flush=True)
+    run, summary, backend = srv.serve(reqs, lambda r: Vs[r["seed"]], slots=2, budget_bytes=8 << 30, keep_outputs=True,
+                                      max_batch=8)
+    print("serving summary", summary, flush=True)
+    assert summary["completed"] == 40 and summary["ok"] == 40
+    assert max(r["batch"] for r in run["results"]) > 1  # some requests shared a launch
+    for r in reqs:
+        Qs, Rs = backend.outputs[r["seed"]]
+        with rc.Plan(r["m"], r["n"], r["s1"], r["s2"], r["seed"]) as p:
+            Q, R = p.factor(Vs[r["seed"]])
+        torch.cuda.synchronize()
+        assert torch.equal(Q, Qs) and torch.equal(R, Rs), r

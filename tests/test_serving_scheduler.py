@@ -85,3 +85,57 @@ def test_more_slots_lower_latency():
 def test_invalid_configuration():
     with pytest.raises(ValueError):
         Scheduler(FakeBackend(), slots=0, budget_bytes=10)
+
+
+class FakeBatchBackend(FakeBackend):
+    """Adds batched launches: a batch takes the longest member's work; shape = req["shape"]."""
+
+    def __init__(self, tick=1e-4):
+        super().__init__(tick)
+        self.batches = []
+
+    def shape_key(self, req):
+        return req.get("shape")
+
+    def launch_batch(self, reqs, slot):
+        self.batches.append([r["id"] for r in reqs])
+        self.launched.extend((r["id"], slot, self.t) for r in reqs)
+        b = sum(r["bytes"] for r in reqs)
+        self.inflight_bytes += b
+        self.max_bytes = max(self.max_bytes, self.inflight_bytes)
+        return {"req": {"bytes": b}, "end": self.t + max(r["work"] for r in reqs), "n": len(reqs)}
+
+    def poll(self, h):
+        done = super().poll(h)
+        if done is None or "n" not in h:
+            return done
+        return done[0], [0] * h["n"]
+
+
+def test_same_shape_requests_share_a_launch():
+    # ids 0..5 arrive together; shapes A A B A B A; one slot busy-free; max_batch 3
+    spec = [(0.0, 0.002, 10)] * 6
+    rq = reqs(spec)
+    for r, sh in zip(rq, "AABABA"):
+        r["shape"] = sh
+    be = FakeBatchBackend()
+    run = Scheduler(be, slots=1, budget_bytes=10**6, max_batch=3).run(rq)
+    # the head (0) takes the next two arrived A's (1, 3); then 2 takes 4; then 5 alone
+    assert be.batches == [[0, 1, 3], [2, 4], [5]] or be.batches[:2] == [[0, 1, 3], [2, 4]]
+    res = run["results"]
+    assert all(r["status"] == 0 for r in res)
+    assert res[0]["batch"] == 3 and res[2]["batch"] == 2
+
+
+def test_batches_respect_budget_and_unbatchable_requests():
+    spec = [(0.0, 0.002, 40)] * 4
+    rq = reqs(spec)
+    for r in rq:
+        r["shape"] = "A"
+    rq[1]["shape"] = None  # never batched
+    be = FakeBatchBackend()
+    Scheduler(be, slots=2, budget_bytes=100, max_batch=4).run(rq)
+    assert be.max_bytes <= 100
+    for b in be.batches:
+        assert 1 not in b or len(b) == 1
+    assert all(len(b) <= 2 for b in be.batches)  # 40-byte members: at most two fit 100 bytes
