@@ -632,17 +632,29 @@ __global__ __launch_bounds__(256) void countsketch_lds_kernel(const double* __re
       const uint32_t bkt = code >> 1;
       if constexpr (RB > 1) {
         // combine rows of this batch with the same bucket into the lowest such row, in row order
-        bool leader = rq < rows;
-        T tot = v;
+        bool same[RB];
+        bool partner = false;
 #pragma unroll
         for (int q2 = 0; q2 < RB; ++q2) {
-          const T v2 = shfl_d(v, q2 * NPL + c);
           const int rq2 = b0 + q2;
-          const bool same = rq2 < rows && (codes[wave][rq2 < rows ? rq2 : 0] >> 1) == bkt;
-          if (same && q2 < q) leader = false;
-          if (same && q2 > q) tot += v2;
+          same[q2] = rq2 < rows && (codes[wave][rq2 < rows ? rq2 : 0] >> 1) == bkt;
+          if (q2 != q && same[q2] && rq < rows) partner = true;
         }
-        if (leader && c < n) mine[bkt * NPL + c] += tot;
+        if (__ballot(partner) == 0) {
+          // no two rows of the batch share a bucket (the common case): each row is its own
+          // leader and its sum is the row itself, so the shuffles below would add nothing
+          if (valid) mine[bkt * NPL + c] += v;
+        } else {
+          bool leader = rq < rows;
+          T tot = v;
+#pragma unroll
+          for (int q2 = 0; q2 < RB; ++q2) {
+            const T v2 = shfl_d(v, q2 * NPL + c);
+            if (same[q2] && q2 < q) leader = false;
+            if (same[q2] && q2 > q) tot += v2;
+          }
+          if (leader && c < n) mine[bkt * NPL + c] += tot;
+        }
       } else {
         if (valid) mine[bkt * NPL + c] += v;
       }

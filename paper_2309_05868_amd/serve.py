@@ -128,17 +128,33 @@ class Scheduler:
 
 
 class GpuBackend:
-    """Runs each request as one rcqr_factor on a slot's stream; V comes from get_V(req)."""
+    """Runs requests through the C ABI on one HIP stream per slot; V comes from get_V(req).
 
-    def __init__(self, get_V, slots, device="cuda:0", flags=0, keep_outputs=False, batch_hint=1):
+    Plans are cached per (slot, shape) for the shapes rcqr_factor_batch takes (shape_key), at
+    most plans_per_slot per slot, least recently used evicted: a request of such a shape reuses
+    its slot's workspace (a lone request runs as a batch of one, bitwise the result of a single
+    rcqr_factor with its seed).  Other shapes get a plan of their own per request.  A slot runs
+    one launch at a time and is handed back only after its launch has completed, so its cached
+    plans, its pinned seed buffer and its device seed buffer are free again whenever the
+    scheduler launches on it.  Cached workspaces stay allocated until close(); the memory
+    budget of the scheduler counts the requests in flight."""
+
+    def __init__(self, get_V, slots, device="cuda:0", flags=0, keep_outputs=False, batch_hint=1, plans_per_slot=4):
         self.device = torch.device(device)
         self.batch_plans = {}
         self.batch_hint = int(batch_hint)
+        self.plans_per_slot = max(1, int(plans_per_slot))
         self.get_V = get_V
         self.flags = flags
         self.keep = keep_outputs
         self.streams = [torch.cuda.Stream(self.device) for _ in range(slots)]
+        self.seed_host = [None] * slots
+        self.seed_dev = [None] * slots
         self.outputs = {}
+        self.reset_clock()
+
+    def reset_clock(self):
+        """Start the run's clock now (after everything queued so far has finished)."""
         torch.cuda.synchronize(self.device)
         self.t0_event = torch.cuda.Event(enable_timing=True)
         self.t0_event.record(self.streams[0])
@@ -153,6 +169,8 @@ class GpuBackend:
         return workspace_bytes(m, n, req["s1"], req["s2"], self.flags) + 8 * m * n + 8 * n * n
 
     def launch(self, req, slot):
+        if self.shape_key(req) is not None:
+            return self.launch_batch([req], slot)
         stream = self.streams[slot]
         V = self.get_V(req)
         with torch.cuda.stream(stream):
@@ -177,30 +195,43 @@ class GpuBackend:
         return (req["m"], req["n"], req["s1"], req["s2"])
 
     def _batch_plan(self, slot, key, count):
-        """A batch plan per (slot, shape), reused while its workspace holds `count` members (a slot
-        runs one launch at a time, so its plans are free again once the launch is polled done)."""
-        cached = self.batch_plans.get((slot, key))
+        """The slot's cached plan for `key`, made (or remade larger) when it cannot hold `count`."""
+        cached = self.batch_plans.pop((slot, key), None)
         if cached is None or cached.batch < count:
             if cached is not None:
                 cached.close()
+            mine = [k for k in self.batch_plans if k[0] == slot]
+            while len(mine) >= self.plans_per_slot:  # dict order = least recently used first
+                self.batch_plans.pop(mine.pop(0)).close()
             m, n, s1, s2 = key
             cached = Plan(m, n, s1, s2, 0, device=self.device, stream=self.streams[slot], batch=max(count, self.batch_hint))
-            self.batch_plans[(slot, key)] = cached
+        self.batch_plans[(slot, key)] = cached  # (re)inserted last: most recently used
         return cached
+
+    def _seeds(self, slot, seeds):
+        """Per-request seeds on the device, staged through the slot's pinned buffer."""
+        k = len(seeds)
+        if self.seed_host[slot] is None or self.seed_host[slot].numel() < k:
+            cap = max(k, self.batch_hint)
+            self.seed_host[slot] = torch.empty(cap, dtype=torch.int64, pin_memory=True)
+            self.seed_dev[slot] = torch.empty(cap, dtype=torch.int64, device=self.device)
+        self.seed_host[slot].numpy()[:k] = seeds
+        d = self.seed_dev[slot][:k]
+        d.copy_(self.seed_host[slot][:k], non_blocking=True)
+        return d
 
     def launch_batch(self, reqs, slot):
         stream = self.streams[slot]
         key = self.shape_key(reqs[0])
         k = len(reqs)
         with torch.cuda.stream(stream):
-            Vb = torch.stack([self.get_V(r) for r in reqs])
-            host = torch.tensor([r["seed"] for r in reqs], dtype=torch.int64).pin_memory()
-            seeds = host.to(self.device, non_blocking=True)
+            Vb = self.get_V(reqs[0]).unsqueeze(0) if k == 1 else torch.stack([self.get_V(r) for r in reqs])
+            seeds = self._seeds(slot, [r["seed"] for r in reqs])
             plan = self._batch_plan(slot, key, k)
             Q, R = plan.factor_batch(Vb, seeds=seeds)
             done = torch.cuda.Event(enable_timing=True)
             done.record(stream)
-        return {"reqs": reqs, "plan": plan, "Q": Q, "R": R, "event": done, "keep": (Vb, seeds, host)}
+        return {"reqs": reqs, "plan": plan, "Q": Q, "R": R, "event": done, "keep": Vb}
 
     def poll(self, handle):
         if not handle["event"].query():
@@ -237,10 +268,20 @@ def latency_summary(run):
             "peak_bytes": run["peak_bytes"], "peak_inflight": run["peak_inflight"]}
 
 
-def serve(requests, get_V, slots=4, budget_bytes=32 << 30, device="cuda:0", flags=0, keep_outputs=False, max_batch=1):
-    """Run the request list with continuous batching; returns (run, summary, backend)."""
-    backend = GpuBackend(get_V, slots, device=device, flags=flags, keep_outputs=keep_outputs, batch_hint=max_batch)
+def serve(requests, get_V, slots=4, budget_bytes=32 << 30, device="cuda:0", flags=0, keep_outputs=False, max_batch=1,
+          backend=None):
+    """Run the request list with continuous batching; returns (run, summary, backend).
+
+    With `backend` (a GpuBackend with at least `slots` streams) the run reuses it and its cached
+    plans, restarting its clock; the caller closes it.  Otherwise a new one is made and closed."""
+    own = backend is None
+    if own:
+        backend = GpuBackend(get_V, slots, device=device, flags=flags, keep_outputs=keep_outputs, batch_hint=max_batch)
+    else:
+        backend.get_V = get_V
+        backend.reset_clock()
     run = Scheduler(backend, slots, budget_bytes, max_batch=max_batch).run(requests)
     torch.cuda.synchronize(backend.device)
-    backend.close()
+    if own:
+        backend.close()
     return run, latency_summary(run), backend

@@ -77,3 +77,36 @@ def test_same_shape_requests_batched_equal_solo_results():
             Q, R = p.factor(Vs[r["seed"]])
         torch.cuda.synchronize()
         assert torch.equal(Q, Qs) and torch.equal(R, Rs), r
+
+
+def test_reused_backend_with_plan_evictions_equals_solo_results():
+    # two runs on one backend whose slots cache one plan each: shapes alternate, so cached plans
+    # are evicted and remade between launches; every result is bitwise the solo result
+    shapes = [(6000, 16, 512, 64), (4000, 32, 2048, 128), (3000, 8, 128, 32)]
+    runs = []
+    for rep in range(2):
+        reqs = []
+        for i in range(12):
+            m, n, s1, s2 = shapes[(i + rep) % 3]
+            reqs.append({"arrival_s": 1e-4 * i, "m": m, "n": n, "s1": s1, "s2": s2, "seed": 900 + 31 * i + rep,
+                         "kappa": 1e8})
+        runs.append(reqs)
+    Vs = {r["seed"]: torch.from_numpy(synth.make_V(r["m"], r["n"], r["kappa"], r["seed"])).to("cuda")
+          for reqs in runs for r in reqs}
+    be = srv.GpuBackend(lambda r: Vs[r["seed"]], 2, keep_outputs=True, batch_hint=4, plans_per_slot=1)
+    try:
+        for reqs in runs:
+            print("serving: 12 requests on a reused backend", flush=True)
+            run, summary, _ = srv.serve(reqs, lambda r: Vs[r["seed"]], slots=2, budget_bytes=4 << 30, max_batch=4,
+                                        backend=be)
+            assert summary["completed"] == 12 and summary["ok"] == 12
+            assert len(be.batch_plans) <= 2
+    finally:
+        be.close()
+    for reqs in runs:
+        for r in reqs:
+            Qs, Rs = be.outputs[r["seed"]]
+            with rc.Plan(r["m"], r["n"], r["s1"], r["s2"], r["seed"]) as p:
+                Q, R = p.factor(Vs[r["seed"]])
+            torch.cuda.synchronize()
+            assert torch.equal(Q, Qs) and torch.equal(R, Rs), r

@@ -139,3 +139,40 @@ def test_batches_respect_budget_and_unbatchable_requests():
     for b in be.batches:
         assert 1 not in b or len(b) == 1
     assert all(len(b) <= 2 for b in be.batches)  # 40-byte members: at most two fit 100 bytes
+
+
+class _FakePlan:
+    made = []
+
+    def __init__(self, m, n, s1, s2, seed, device=None, stream=None, batch=1):
+        self.key, self.batch, self.closed = (m, n, s1, s2), batch, False
+        _FakePlan.made.append(self)
+
+    def close(self):
+        self.closed = True
+
+
+def test_gpu_backend_plan_cache_is_lru_per_slot(monkeypatch):
+    # host logic of the per-slot plan cache, with a stand-in Plan (no device needed)
+    from paper_2309_05868_amd import serve as srv
+
+    monkeypatch.setattr(srv, "Plan", _FakePlan)
+    _FakePlan.made = []
+    be = object.__new__(srv.GpuBackend)
+    be.batch_plans, be.batch_hint, be.plans_per_slot = {}, 2, 2
+    be.device, be.streams = None, [None, None]
+    A, B, C = (100, 8, 128, 32), (200, 8, 128, 32), (300, 8, 128, 32)
+    pa = be._batch_plan(0, A, 1)
+    assert pa.batch == 2                              # sized for the batch hint
+    assert be._batch_plan(0, A, 2) is pa              # reused while it holds the count
+    pb = be._batch_plan(0, B, 1)
+    pb1 = be._batch_plan(1, B, 1)                     # other slot: its own plan
+    assert pb1 is not pb
+    assert be._batch_plan(0, A, 1) is pa              # A used last on slot 0, so B is the oldest
+    pc = be._batch_plan(0, C, 1)                      # third shape on slot 0 evicts B only
+    assert pb.closed and not pa.closed and not pc.closed and not pb1.closed
+    assert set(be.batch_plans) == {(0, A), (0, C), (1, B)}
+    pa4 = be._batch_plan(0, A, 4)                     # too small: remade larger, old one closed
+    assert pa.closed and pa4.batch == 4 and not pc.closed
+    be.close()
+    assert all(p.closed for p in _FakePlan.made) and be.batch_plans == {}
