@@ -78,7 +78,7 @@ def _gpu():
     rc.lib()
 
 
-@pytest.mark.parametrize("m,n,s1", [(10_000, 16, 256), (50_000, 64, 8192), (20_000, 128, 1000)])
+@pytest.mark.parametrize("m,n,s1", [(10_000, 16, 256), (10_000, 16, 512), (50_000, 64, 8192), (20_000, 128, 1000)])
 def test_fp32_countsketch_integer_bit_exact(m, n, s1):
     say("fp32 countsketch int", m, n, s1)
     V = synth.make_int_V(m, n, seed=m + n)

@@ -78,9 +78,10 @@ def test_gaussian_entries_match_oracle():
 
 
 # (m, n, s1): LDS CountSketch (s1 * padded n <= 4096) and bucket-index CountSketch, including
-# buckets longer than one sort window (m / s1 > 2048).
+# buckets longer than one sort window (m / s1 > 2048), ragged n and s1 just above the LDS limit.
 CS_CASES = [(5000, 8, 128), (10_000, 16, 256), (20_001, 16, 512), (50_000, 64, 8192), (3001, 32, 2048),
-            (600_000, 64, 100), (9999, 50, 700), (20_000, 128, 1000), (4321, 100, 333)]
+            (600_000, 64, 100), (9999, 50, 700), (20_000, 128, 1000), (4321, 100, 333),
+            (70_001, 10, 500), (30_000, 32, 256), (20_000, 64, 128), (300_000, 16, 512)]
 
 
 @pytest.mark.parametrize("m,n,s1", CS_CASES)
