@@ -278,6 +278,8 @@ def serve(requests, get_V, slots=4, budget_bytes=32 << 30, device="cuda:0", flag
     if own:
         backend = GpuBackend(get_V, slots, device=device, flags=flags, keep_outputs=keep_outputs, batch_hint=max_batch)
     else:
+        if slots > len(backend.streams):
+            raise ValueError(f"{slots} slots need as many streams; the backend has {len(backend.streams)}")
         backend.get_V = get_V
         backend.reset_clock()
     run = Scheduler(backend, slots, budget_bytes, max_batch=max_batch).run(requests)

@@ -176,3 +176,12 @@ def test_gpu_backend_plan_cache_is_lru_per_slot(monkeypatch):
     assert pa.closed and pa4.batch == 4 and not pc.closed
     be.close()
     assert all(p.closed for p in _FakePlan.made) and be.batch_plans == {}
+
+
+def test_serve_rejects_more_slots_than_backend_streams():
+    from paper_2309_05868_amd import serve as srv
+
+    be = object.__new__(srv.GpuBackend)
+    be.streams = [None, None]
+    with pytest.raises(ValueError):
+        srv.serve([], lambda r: None, slots=3, backend=be)
