@@ -106,8 +106,16 @@ hipError_t prepare_cholesky(int np);
 hipError_t launch_identity_factor(int n, int np, double* r0, double* r0pk, hipStream_t s);
 
 // --- stream.hip ------------------------------------------------------------------------------
-constexpr int kGramBlocks = 256;     // workgroups of the Gram pass (fixed: fixes the sum order)
+constexpr int kGramBlocks = 256;     // most workgroups of the Gram pass (the count fixes the sum order)
 constexpr int kGramThreads = 512;
+// Workgroups of the Gram pass (and Gram partials) for m rows: one per eight 64-row tiles (one
+// tile per wave), at most kGramBlocks.  A function of m alone, so the summation order is fixed
+// by the shape; a small matrix does not pay for kGramBlocks partials that would hold zeros.
+inline int gram_blocks(int64_t m) {
+  const int64_t per = kGramThreads;  // eight waves, one 64-row tile each
+  const int64_t b = (m + per - 1) / per;
+  return b < 1 ? 1 : (b > kGramBlocks ? kGramBlocks : (int)b);
+}
 int gram_compact_len(int np);        // doubles per compact Gram partial
 int packed_len(int np);              // doubles of a packed np x np triangular factor
 // Packed factor format (R padded to np columns with an identity block): the upper triangle

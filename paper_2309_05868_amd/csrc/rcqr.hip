@@ -256,7 +256,8 @@ static rcqr_status_t run_gram(rcqr_plan_t p, const double* V, int64_t ldv, const
     RCQR_TRY(launch_solve128(V, sh.m, (int)sh.n, ldv, rpk, info, Q, ldq, p->stream, p->grid_mult));
     RCQR_TRY(launch_syrk128(Q, sh.m, (int)sh.n, ldq, info, p->at<double>(p->L.gpart), p->stream));
   }
-  RCQR_TRY(launch_reduce_parts(p->at<double>(p->L.gpart), kGramBlocks, len, len, p->at<double>(p->L.gc), p->stream));
+  const int nparts = sh.np <= 64 ? gram_blocks(sh.m) : kGramBlocks;  // the 65-128-column Gram keeps the full grid
+  RCQR_TRY(launch_reduce_parts(p->at<double>(p->L.gpart), nparts, len, len, p->at<double>(p->L.gc), p->stream));
   return RCQR_OK;
 }
 
@@ -486,7 +487,7 @@ rcqr_status_t rcqr_factor_batch(rcqr_plan_t p, int32_t count, const double* V, i
   RCQR_TRY(launch_finalize_r0(p->at<double>(L.qra), n, sh.np, info, p->at<double>(L.r0), p->at<double>(L.r0pk), s, ms));
   RCQR_TRY(launch_trsm_gram(sh.np, V, sh.m, n, ldv, p->at<double>(L.r0pk), info, p->at<double>(L.gpart), nullptr, ldq, s, ms));
   const int64_t len = gram_compact_len(sh.np);
-  RCQR_TRY(launch_reduce_parts(p->at<double>(L.gpart), kGramBlocks, len, len, p->at<double>(L.gc), s, ms));
+  RCQR_TRY(launch_reduce_parts(p->at<double>(L.gpart), gram_blocks(sh.m), len, len, p->at<double>(L.gc), s, ms));
   RCQR_TRY(launch_cholesky(p->at<double>(L.gc), n, sh.np, p->at<double>(L.r0), 0.0, info, p->at<double>(L.g), p->at<double>(L.r1),
                            p->at<double>(L.r1pk), R, ldr, s, ms));
   RCQR_TRY(launch_final(sh.np, true, V, sh.m, n, ldv, p->at<double>(L.r0pk), p->at<double>(L.r1pk), info, Q, ldq, s, p->grid_mult, ms));

@@ -490,7 +490,7 @@ static bool full_rows(int np, int n, const void* a, int64_t lda, const void* b, 
 hipError_t launch_trsm_gram(int np, const double* V, int64_t m, int n, int64_t ldv, const double* r0pk, const int32_t* info,
                             double* gpart, double* q0, int64_t ldq, hipStream_t s, const MemberStride& ms) {
   if (ms.count < 1) return hipErrorInvalidValue;
-  const dim3 grid(kGramBlocks, ms.count), block(kGramThreads);
+  const dim3 grid(gram_blocks(m), ms.count), block(kGramThreads);
   const bool full = full_rows(np, n, V, ldv, q0, ldq) && ms.v % 2 == 0 && ms.q % 2 == 0;
 #define RCQR_GRAM_B(NPV, B)                                                                                                       \
   if (full && q0)                                                                                                                 \

@@ -215,8 +215,11 @@ class GpuBackend:
             cap = max(k, self.batch_hint)
             self.seed_host[slot] = torch.empty(cap, dtype=torch.int64, pin_memory=True)
             self.seed_dev[slot] = torch.empty(cap, dtype=torch.int64, device=self.device)
-        self.seed_host[slot].numpy()[:k] = seeds
         d = self.seed_dev[slot][:k]
+        if k == 1:  # a lone request: the seed goes in as a fill kernel's argument, no copy
+            d.fill_(int(seeds[0]))
+            return d
+        self.seed_host[slot].numpy()[:k] = seeds
         d.copy_(self.seed_host[slot][:k], non_blocking=True)
         return d
 
