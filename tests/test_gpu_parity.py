@@ -253,3 +253,27 @@ def test_scholqr3_comparator(n, s1, s2, k_mid):
         Q = host(Q)
         assert np.linalg.norm(np.eye(n) - Q.T @ Q) <= tgt
 
+
+
+# Gram pass grid: one workgroup per 512 rows (eight 64-row tiles), at most 256 -- one, two and
+# 256 workgroups and the cap
+@pytest.mark.parametrize("m", [64, 511, 512, 513, 131_072, 131_073])
+def test_gram_grid_edges(m):
+    n, s1, s2 = 16, 512, 64
+    say("gram grid", m)
+    V = synth.make_V(m, n, 1e4, seed=17)
+    with rc.Plan(m, n, s1, s2, seed=17) as p:
+        Q, R = p.factor(dev(V))
+        G = host(p.intermediates()["G"])
+        Q0a, Q0b = p.q0_twice(dev(V))
+        Q0 = host(Q0a)
+        assert np.array_equal(Q0, host(Q0b))
+    Q, R = host(Q), host(R)
+    # the device Gram against the Gram of the device Q0, entrywise within m u |Q0|^T |Q0|: a
+    # workgroup partial dropped or counted twice would be off by whole tiles
+    bound = m * U_PAPER * (np.abs(Q0).T @ np.abs(Q0))
+    assert np.all(np.abs(np.triu(G) - np.triu(Q0.T @ Q0)) <= np.triu(bound))
+    tgt = 10 * n * U_PAPER
+    assert np.linalg.norm(np.eye(n) - Q.T @ Q) <= tgt
+    assert np.linalg.norm(V - Q @ R) / np.linalg.norm(V) <= tgt
+    assert rel(R, lapack_r(V)) <= 1e-10
