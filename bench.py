@@ -11,9 +11,12 @@ kappa(V) = 1e12, CountSketch s1 = 8192, Gaussian s2 = 256, seed 1.
 Prints one JSON line: QR/s (value), algorithmic GB/s (32 m n bytes per factorization), the
 roofline of the dominant kernel (HIP-event durations measured inside the timed region), the
 accuracy of the result, cholQR2 and shifted CholeskyQR3 run on the same V and GPU (after the
-timed region), and the CPU oracle timed on a bounded sample of the same workload.
+timed region), and, after the timed region: the 2,097,152 x 128 FP64 sweep shape (fp64_2097152x128),
+the serving configuration's p50 / p99 latency and QR/s against one request at a time (served),
+the CPU oracle timed on a bounded sample of the same workload (cpu_baseline), and CPU cholQR2 and
+shifted CholeskyQR3 with BLAS-3 on every host core at full size (cpu_blas3, cpu_host).
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-comparators]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-comparators] [--no-serve] [--no-n128]
   python bench.py --workload mixed     # precision variants, m = 4e6, n = 128, kappa = 1e14
   python bench.py --workload serve     # 4096 requests, continuous batching vs one at a time
   python bench.py --workload latency   # small factorizations, eager vs HIP graph
@@ -42,7 +45,7 @@ MIXED_WORKLOAD = dict(m=4_000_000, n=128, kappa=1e14, s1=32768, s2=512, seed=3)
 # serving: Poisson arrivals, log-uniform m, uniform n, log-uniform kappa (snapped to a bank of bases)
 SERVE_WORKLOAD = dict(count=4096, rate_per_s=2000.0, seed=4, m_range=(1e4, 2e6), n_choices=(8, 16, 32, 64, 128),
                       kappa_range=(1e2, 1e15))
-SERVE_KAPPA_BANK = [10.0 ** e for e in (2.0, 4.6, 7.2, 9.8, 12.4, 15.0)]
+SERVE_KAPPA_BANK = [10.0 ** (2.0 + 13.0 * i / 11.0) for i in range(12)]
 MIXED_VARIANTS = [("fp64", 0), ("fp32_sketch", 1), ("bf16_gemm", 3), ("fp64_reorth", 4), ("fp32_sketch_reorth", 5),
                   ("bf16_gemm_reorth", 7)]
 
@@ -197,9 +200,22 @@ def mixed_variants(args):
     print(json.dumps(line), flush=True)
 
 
-def serve_workload(args):
-    """Continuous batching over several streams against one request at a time (per-request plain
-    launches), on the same request list: completed QR/s and p50 / p99 latency."""
+def device_basis(m, n, seed, dev):
+    """U (m x n, orthonormal columns) and W (n x n orthogonal): Q factors of seeded standard normal
+    matrices drawn and factored on the device (the recipe of make_V, built where V lives)."""
+    import torch
+
+    g = torch.Generator(device=dev)
+    g.manual_seed(int(seed))
+    U, _ = torch.linalg.qr(torch.randn((m, n), generator=g, dtype=torch.float64, device=dev))
+    W, _ = torch.linalg.qr(torch.randn((n, n), generator=g, dtype=torch.float64, device=dev))
+    return U.contiguous(), W
+
+
+def serve_c4(args, dev):
+    """The serving configuration: continuous batching over several streams against one request at a
+    time (per-request plain launches), on the same request list.  Returns the per-mode summaries
+    (completed QR/s, p50 / p99 latency) and the worst sampled error over 10 n u."""
     import numpy as np
     import torch
 
@@ -208,16 +224,14 @@ def serve_workload(args):
     from paper_2309_05868_amd import serve as srv
 
     wl = SERVE_WORKLOAD
-    dev = torch.device("cuda:0")
     reqs = synth.make_requests(wl["count"], wl["seed"], rate_per_s=wl["rate_per_s"], m_range=wl["m_range"],
                                n_choices=wl["n_choices"], kappa_range=wl["kappa_range"])
     m_max = max(r["m"] for r in reqs)
     bank = {}
     for n in wl["n_choices"]:
         log(f"bench: serving bank n={n}")
-        U, _, W = synth.make_factors(m_max, n, 1.0, seed=5000 + n)
-        Ud, Wt = torch.from_numpy(U).to(dev), torch.from_numpy(np.ascontiguousarray(W.T)).to(dev)
-        del U
+        Ud, W = device_basis(m_max, n, 5000 + n, dev)
+        Wt = W.T.contiguous()
         for kb in SERVE_KAPPA_BANK:
             sig = torch.from_numpy(synth.singular_values(n, kb)).to(dev)
             bank[(n, kb)] = (Ud * sig) @ Wt
@@ -252,19 +266,83 @@ def serve_workload(args):
         orth = torch.linalg.norm(eye - gram_accurate(Q)).item()
         res = (torch.linalg.norm(V - Q @ R) / torch.linalg.norm(V)).item()
         worst = max(worst, orth / (10 * n * U_PAPER), res / (10 * n * U_PAPER))
+    del bank
+    torch.cuda.empty_cache()
+    workload = (f"rand_cholQR serving: {wl['count']} requests, Poisson {wl['rate_per_s']:.0f}/s, m log-uniform "
+                f"[{wl['m_range'][0]:.0e}, {wl['m_range'][1]:.0e}], n in {list(wl['n_choices'])}, kappa log-uniform "
+                f"[{wl['kappa_range'][0]:.0e}, {wl['kappa_range'][1]:.0e}], s1 = 2n^2, s2 = 4n")
+    note = (f"V = leading m rows of a device-resident base U diag(sigma) W^T per n with the nearest of "
+            f"{len(SERVE_KAPPA_BANK)} log-spaced kappa values; latency = device completion - arrival")
+    return {"workload": workload, "modes": out, "sample_worst_error_over_10nu": worst, "note": note,
+            "warmup_requests": len(warm)}
+
+
+def serve_workload(args):
+    import torch
+
+    res = serve_c4(args, torch.device("cuda:0"))
+    cb = res["modes"]["continuous_batching"]
     line = {
-        "metric": METRIC, "value": out["continuous_batching"].get("qr_per_s"), "unit": "QR/s", "n_gpus": 1,
-        "steps": len(reqs), "warmup": len(warm), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"rand_cholQR serving: {wl['count']} requests, Poisson {wl['rate_per_s']:.0f}/s, "
-                               f"m log-uniform [{wl['m_range'][0]:.0e}, {wl['m_range'][1]:.0e}], n in {list(wl['n_choices'])}, "
-                               f"kappa log-uniform [{wl['kappa_range'][0]:.0e}, {wl['kappa_range'][1]:.0e}], s1 = 2n^2, s2 = 4n"},
-        "p50_ms": out["continuous_batching"].get("p50_ms"), "p99_ms": out["continuous_batching"].get("p99_ms"),
-        "modes": out, "sample_worst_error_over_10nu": worst,
-        "note": "V = leading m rows of a resident base with the nearest of 6 log-spaced kappa values; "
-                "latency = device completion - arrival",
+        "metric": METRIC, "value": cb.get("qr_per_s"), "unit": "QR/s", "n_gpus": 1,
+        "steps": SERVE_WORKLOAD["count"], "warmup": res["warmup_requests"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": {"workload": res["workload"]},
+        "p50_ms": cb.get("p50_ms"), "p99_ms": cb.get("p99_ms"), "modes": res["modes"],
+        "sample_worst_error_over_10nu": res["sample_worst_error_over_10nu"], "note": res["note"],
     }
     print(json.dumps(line), flush=True)
+
+
+N128_WORKLOAD = dict(m=2_097_152, n=128, kappa=1e8, s1=32768, s2=512, seed=228)
+
+
+def n128_line(args, dev):
+    """Plain FP64 at the 128-column sweep shape (m = 2,097,152, kappa = 1e8, s1 = 2 n^2, s2 = 4 n):
+    time, algorithmic GB/s, fractions of the HBM roof and of the FP64 roof (which binds at
+    n = 128: 4 n^2 m flops), orthogonality and residual."""
+    import torch
+
+    import paper_2309_05868_amd as rc
+    import synth
+
+    wl = N128_WORKLOAD
+    m, n = wl["m"], wl["n"]
+    log(f"bench: {m} x {n} line")
+    Ud, W = device_basis(m, n, wl["seed"], dev)
+    sig = torch.from_numpy(synth.singular_values(n, wl["kappa"])).to(dev)
+    V = (Ud * sig) @ W.T.contiguous()
+    del Ud
+    Q = torch.empty_like(V)
+    R = torch.empty((n, n), dtype=torch.float64, device=dev)
+    with rc.Plan(m, n, wl["s1"], wl["s2"], wl["seed"], device=dev) as plan:
+        for _ in range(2):
+            plan.factor(V, Q, R, check=False)
+        plan.raise_on_failure("n128 warmup")
+        steps = max(3, args.steps // 4)
+        plan.set_timing(steps)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(plan.stream)
+        for _ in range(steps):
+            plan.factor(V, Q, R, check=False)
+        ev1.record(plan.stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / steps
+        phases = plan.phase_times()
+        plan.raise_on_failure("n128 timed steps")
+    eye = torch.eye(n, dtype=torch.float64, device=dev)
+    orth = torch.linalg.norm(eye - gram_accurate(Q)).item()
+    res = (torch.linalg.norm(V - Q @ R) / torch.linalg.norm(V)).item()
+    t_hbm = 32.0 * m * n / (HBM_PEAK_GBS * 1e9)
+    t_fp64 = 4.0 * n * n * m / (FP64_PEAK_TFLOPS * 1e12)
+    del V, Q
+    torch.cuda.empty_cache()
+    return {"config": {k: wl[k] for k in ("m", "n", "kappa", "s1", "s2", "seed")}, "steps": steps,
+            "ms_per_qr": round(ms, 4), "qr_per_s": round(1000.0 / ms, 2),
+            "gbps_algorithmic": round(32.0 * m * n / (ms * 1e-3) / 1e9, 1),
+            "hbm_frac_algorithmic": round(t_hbm / (ms * 1e-3), 4),
+            "binding_roof_frac": round(max(t_hbm, t_fp64) / (ms * 1e-3), 4),
+            "phase_ms": {k: round(v, 4) for k, v in phases.items()},
+            "orth_error": orth, "residual": res, "within_target": bool(orth <= 10 * n * U_PAPER and res <= 10 * n * U_PAPER)}
 
 
 SERVE_SMALL = dict(count=4096, rate_per_s=200_000.0, m=10_000, n=16, s1=512, s2=64, bank=16, seed=12)
@@ -529,26 +607,103 @@ def batch_workload(args):
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(wl, sample_rows):
-    """The oracle as it stands, single-threaded, on a row-scaled sample of the workload."""
+def host_info():
+    """Cores this process may use, the CPU model and the BLAS thread count (for the CPU baselines)."""
+    from threadpoolctl import threadpool_info
+
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = [d for d in threadpool_info() if d.get("user_api") == "blas"]
+    return {"cores": len(os.sched_getaffinity(0)), "cpu_model": model,
+            "blas": blas[0].get("internal_api") if blas else None, "blas_threads": blas[0].get("num_threads") if blas else None}
+
+
+def cpu_baseline(wl, sample_rows, reps=3):
+    """The oracle as it stands, single-threaded, on a row-scaled sample of the workload (median of
+    `reps` runs)."""
     from threadpoolctl import threadpool_limits
 
     import synth
     from oracle.rand_cholqr import rand_cholqr
 
     V = synth.make_V(sample_rows, wl["n"], wl["kappa"], wl["seed"])
+    times = []
     with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        o = rand_cholqr(V, wl["s1"], wl["s2"], wl["seed"])
-        dt = time.perf_counter() - t0
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            o = rand_cholqr(V, wl["s1"], wl["s2"], wl["seed"])
+            times.append(time.perf_counter() - t0)
     if o["status"] != 0:
         raise RuntimeError("oracle failed on the CPU sample")
+    dt = sorted(times)[len(times) // 2]
     scale = wl["m"] / sample_rows
     return {
         "value": 1.0 / (dt * scale), "unit": "QR/s", "cores": 1, "kind": "oracle",
         "sample": f"oracle rand_cholQR on {sample_rows} x {wl['n']} rows of the same recipe (kappa {wl['kappa']:.0e}, "
-                  f"s1 {wl['s1']}, s2 {wl['s2']}), {dt:.2f} s, scaled linearly in rows to m = {wl['m']}",
+                  f"s1 {wl['s1']}, s2 {wl['s2']}), median of {reps} runs {dt:.2f} s (one thread), scaled linearly in rows "
+                  f"to m = {wl['m']}",
     }
+
+
+def cpu_blas3_comparators(V_hard, V_easy, reps=3):
+    """CPU Cholesky QR2 (Algorithm 4) and shifted CholeskyQR3 with BLAS-3 on every host core, at the
+    full workload size: timed (median of `reps`) on V_easy of the workload's shape, where both
+    complete, and their status on V_hard (the workload's V).  Baselines for the GPU numbers."""
+    import numpy as np
+    import scipy.linalg as sla
+
+    u = 2.0 ** -52
+
+    def chol_upper(G):
+        return sla.cholesky(G, lower=False, check_finite=False)
+
+    def solve_right(X, Rm):  # X Rm^{-1} (Rm upper triangular): Rm^T Y^T = X^T
+        return sla.solve_triangular(Rm, X.T, trans="T", lower=False, check_finite=False).T
+
+    def cholqr(X):
+        Rm = chol_upper(X.T @ X)
+        return solve_right(X, Rm), Rm
+
+    def cholqr2(X):
+        Q1, R1 = cholqr(X)
+        Q2, R2 = cholqr(Q1)
+        return Q2, R2 @ R1
+
+    def scholqr3(X):
+        m, n = X.shape
+        G = X.T @ X
+        shift = 11.0 * (m * n + n * (n + 1)) * u * float(np.trace(G))
+        Ra = chol_upper(G + shift * np.eye(n))
+        Q, Rbc = cholqr2(solve_right(X, Ra))
+        return Q, Rbc @ Ra
+
+    out = {}
+    for name, fn in (("cholqr2", cholqr2), ("scholqr3", scholqr3)):
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            Q, Rm = fn(V_easy)
+            times.append(time.perf_counter() - t0)
+        n = V_easy.shape[1]
+        dt = sorted(times)[len(times) // 2]
+        rec = {"qr_per_s": round(1.0 / dt, 3), "ms_per_qr": round(1e3 * dt, 1),
+               "orth_error_easy": float(np.linalg.norm(np.eye(n) - Q.T @ Q))}
+        try:
+            Q, Rm = fn(V_hard)
+            ok = bool(np.all(np.isfinite(Q)))
+            rec["orth_error_workload"] = float(np.linalg.norm(np.eye(n) - Q.T @ Q)) if ok else None
+            rec["status_workload"] = "ok" if ok else "non-finite"
+        except np.linalg.LinAlgError:
+            rec["status_workload"] = "cholesky breakdown"
+        out[name] = rec
+    return out
 
 
 def main():
@@ -557,6 +712,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving configuration in the default run")
+    ap.add_argument("--no-n128", action="store_true", help="skip the 2,097,152 x 128 FP64 line in the default run")
     ap.add_argument("--no-comparators", action="store_true", help="skip timing cholQR2 and sCholQR3 on the same V")
     ap.add_argument("--tune", action="store_true", help="run rcqr_tune (result-neutral launch choices) before warm-up")
     ap.add_argument("--comparator-steps", type=int, default=5)
@@ -691,10 +848,28 @@ def main():
     }
     if not args.no_comparators:
         out["comparators"] = comparators(plan, V, Q, R, eye, tgt, args.comparator_steps)
+    plan.close()
+    Q_host = Q.cpu().numpy() if not args.no_cpu_baseline else None
+    del Q, R
+    torch.cuda.empty_cache()
+    if not args.no_n128:
+        out["fp64_2097152x128"] = n128_line(args, dev)
+    if not args.no_serve:
+        sv = serve_c4(args, dev)
+        cb, one = sv["modes"]["continuous_batching"], sv["modes"]["one_at_a_time"]
+        out["served"] = {"workload": sv["workload"], "p50_ms": cb.get("p50_ms"), "p99_ms": cb.get("p99_ms"),
+                         "qr_per_s": cb.get("qr_per_s"), "one_at_a_time": {k: one.get(k) for k in ("p50_ms", "p99_ms", "qr_per_s")},
+                         "continuous_batching": cb, "sample_worst_error_over_10nu": sv["sample_worst_error_over_10nu"],
+                         "note": sv["note"]}
     if not args.no_cpu_baseline:
         log(f"bench: cpu baseline on {args.cpu_sample_rows} rows")
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_rows)
-    plan.close()
+        out["cpu_host"] = host_info()
+        log("bench: CPU cholQR2 / shifted CholeskyQR3 with BLAS-3 on all cores")
+        cb3 = cpu_blas3_comparators(V_host, Q_host)
+        cb3["note"] = (f"full size {m} x {n}, every host core ({out['cpu_host']['blas_threads']} BLAS threads), median of 3, "
+                       f"timed on the GPU's Q of the workload (same shape, kappa 1), status on the workload's V")
+        out["cpu_blas3"] = cb3
     print(json.dumps(out), flush=True)
 
 

@@ -85,7 +85,10 @@ typedef enum {
 #define RCQR_FLAG_REORTH 4u
 
 /* Bytes of device workspace a plan of this shape needs (0 if the shape or the flags are
- * invalid; the flags do not change the size). */
+ * invalid; the flags do not change the size).  It holds the small intermediates of Algorithm 1
+ * (W1 = S1 V of s1 x n, W = S2 W1 of s2 x n, R0) and Algorithm 2 (G, R1), the partial sums of
+ * the multi-workgroup passes, the CountSketch bucket index (about 8 bytes per row of V when
+ * s1 n exceeds the LDS copies) and the status word; never a copy of V or Q0. */
 size_t rcqr_workspace_bytes(int64_t m, int64_t n, int64_t s1, int64_t s2, uint32_t flags);
 
 /*
@@ -103,7 +106,9 @@ rcqr_status_t rcqr_plan(rcqr_plan_t* plan, int64_t m, int64_t n, int64_t s1, int
 /*
  * Algorithm 3 (rand_cholQR): W = S2 (S1 V); R0 = Householder R of W (Algorithm 1); Q0 = V R0^{-1}
  * by row-wise substitution; G = Q0^T Q0; R1 = chol(G) (Algorithm 2); Q = Q0 R1^{-1};
- * R = R1 R0.  Asynchronous on the plan's stream.
+ * R = R1 R0.  Asynchronous on the plan's stream.  In place (d_Q == d_V) is supported except
+ * for a plan with RCQR_FLAG_REORTH and more than 64 columns, which returns RCQR_E_INVALID
+ * (that path stores Q0 in Q and then reads V a second time).
  */
 rcqr_status_t rcqr_factor(rcqr_plan_t plan, const double* d_V, int64_t ldv, double* d_Q, int64_t ldq,
                           double* d_R, int64_t ldr);
@@ -128,10 +133,15 @@ rcqr_status_t rcqr_scholqr3(rcqr_plan_t plan, const double* d_V, int64_t ldv, do
                             double* d_R, int64_t ldr);
 
 /* Wait for the plan's stream and report the last factorization: *status is an rcqr_status_t
- * (RCQR_OK, RCQR_E_RANK or RCQR_E_CHOL), *column the 1-based failing column or 0. */
+ * (RCQR_OK, RCQR_E_RANK or RCQR_E_CHOL), *column the 1-based failing column or 0.  Algorithm 1
+ * needs W = S2 S1 V of full column rank (the remark after Algorithm 1 in Section 4) and
+ * Algorithm 2 a positive definite Gram matrix: RANK names the first column whose R0 diagonal
+ * entry is zero or not finite, CHOL the first non-positive pivot of chol(G). */
 rcqr_status_t rcqr_info(rcqr_plan_t plan, int32_t* status, int32_t* column);
 
-/* Free the host-side plan; does not touch the caller's memory. */
+/* Free the host-side plan (the handle rcqr_plan returned for Algorithm 3's shape and sketch
+ * sizes); does not touch the caller's memory, which the caller frees after the plan's stream
+ * has passed the last call that uses it. */
 rcqr_status_t rcqr_destroy(rcqr_plan_t plan);
 
 /* Static description of a status code. */
@@ -261,16 +271,26 @@ rcqr_status_t rcqr_sketch_hash(rcqr_plan_t plan, int64_t row0, int64_t count, in
  * leading dimension nk, into device memory d_out (nj * nk doubles). */
 rcqr_status_t rcqr_gaussian_block(rcqr_plan_t plan, int64_t j0, int64_t nj, int64_t k0, int64_t nk, double* d_out);
 
-/* Copy the intermediates of the last rcqr_factor call from the workspace (device to device):
- * W1 (s1 x n), W (s2 x n), R0 (n x n), G (n x n, upper triangle; lower set to zero),
- * R1 (n x n).  Any pointer may be NULL.  With RCQR_FLAG_SKETCH_FP32, W1 and W are the FP32
- * values widened to FP64; with RCQR_FLAG_REORTH, G and R1 are those of the second pass. */
+/* Copy the intermediates of the last rcqr_factor call from the workspace (device to device),
+ * in the notation of Algorithms 1 and 2: W1 = S1 V (s1 x n), W = S2 W1 (s2 x n), R0 = the
+ * Householder R of W (n x n), G = Q0^T Q0 (n x n, upper triangle; lower set to zero),
+ * R1 = chol(G) (n x n).  Any pointer may be NULL; the caller owns the destinations (row-major,
+ * leading dimension = number of columns).  With RCQR_FLAG_SKETCH_FP32, W1 and W are the FP32
+ * values widened to FP64; with RCQR_FLAG_REORTH, G and R1 are those of the second pass.
+ * Asynchronous on the plan's stream; RCQR_E_INVALID for a null plan. */
 rcqr_status_t rcqr_intermediates(rcqr_plan_t plan, double* d_W1, double* d_W, double* d_R0, double* d_G,
                                  double* d_R1);
 
-/* Q0 = V R0^{-1} as computed inside the Gram pass (d_Q0_gram) and as recomputed inside the
- * final pass (d_Q0_final), using R0 of the last rcqr_factor call on the same V.  The method
- * relies on the two being bitwise identical.  Both outputs m x n with leading dimension ldq. */
+/* Q0 = V R0^{-1} (Algorithm 1, step 3, by the row-wise substitution Section 5.2 analyses) as
+ * computed inside the Gram pass (d_Q0_gram) and as recomputed inside the final pass
+ * (d_Q0_final), using R0 of the last rcqr_factor call on the same V.  Up to 64 columns these are
+ * the kernels rcqr_factor launches: the Gram pass in the variant that stores Q0 (the
+ * materialising launch choice) and the final pass given R1 = I, whose product by the identity
+ * returns its recomputed Q0 unchanged.  The recompute scheme relies on the two being bitwise
+ * identical: the Gram matrix that gave R1 must be the Gram matrix of the Q0 that R1 is applied
+ * to.  65..128 columns store Q0 and do not recompute it (both outputs come from the same solve).
+ * Both outputs m x n with leading dimension ldq, caller-owned device memory.  Overwrites the
+ * plan's Gram partials; asynchronous on the plan's stream. */
 rcqr_status_t rcqr_q0_twice(rcqr_plan_t plan, const double* d_V, int64_t ldv, double* d_Q0_gram,
                             double* d_Q0_final, int64_t ldq);
 

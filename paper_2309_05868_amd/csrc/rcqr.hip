@@ -391,6 +391,8 @@ static rcqr_status_t check_io(rcqr_plan_t p, const double* V, int64_t ldv, doubl
 rcqr_status_t rcqr_factor(rcqr_plan_t p, const double* V, int64_t ldv, double* Q, int64_t ldq, double* R, int64_t ldr) {
   const rcqr_status_t st = check_io(p, V, ldv, Q, ldq, R, ldr);
   if (st != RCQR_OK) return st;
+  // 65..128 columns store Q0 in Q; the second Cholesky QR reads V again, so V must survive
+  if ((p->flags & RCQR_FLAG_REORTH) && p->sh.np > 64 && (const void*)Q == (const void*)V) return RCQR_E_INVALID;
   const Shape& sh = p->sh;
   const Layout& L = p->L;
   const int n = (int)sh.n;
@@ -867,10 +869,15 @@ rcqr_status_t rcqr_q0_twice(rcqr_plan_t p, const double* V, int64_t ldv, double*
   const Shape& sh = p->sh;
   const Layout& L = p->L;
   if (sh.np <= 64) {
+    // the Gram pass as the materialising mode runs it (Q0 stored from its LDS staging), and the
+    // final pass the factorization runs, given R1 = I: its product by the identity adds only
+    // zeros to each x_k (one MFMA term is x_k * 1, the others 0 * R), so it returns the Q0 rows
+    // it recomputed unchanged
     RCQR_TRY(launch_trsm_gram(sh.np, V, sh.m, (int)sh.n, ldv, p->at<double>(L.r0pk), p->at<int32_t>(L.info), p->at<double>(L.gpart),
                               Q0a, ldq, p->stream));
-    RCQR_TRY(launch_final(sh.np, false, V, sh.m, (int)sh.n, ldv, p->at<double>(L.r0pk), p->at<double>(L.r1pk),
-                          p->at<int32_t>(L.info), Q0b, ldq, p->stream));
+    RCQR_TRY(launch_identity_factor((int)sh.n, sh.np, p->at<double>(L.ra), p->at<double>(L.rapk), p->stream));
+    RCQR_TRY(launch_final(sh.np, true, V, sh.m, (int)sh.n, ldv, p->at<double>(L.r0pk), p->at<double>(L.rapk),
+                          p->at<int32_t>(L.info), Q0b, ldq, p->stream, p->grid_mult));
   } else {  // Q0 is stored, not recomputed: both outputs come from the same solve
     RCQR_TRY(launch_solve128(V, sh.m, (int)sh.n, ldv, p->at<double>(L.r0pk), p->at<int32_t>(L.info), Q0a, ldq, p->stream));
     RCQR_TRY(launch_solve128(V, sh.m, (int)sh.n, ldv, p->at<double>(L.r0pk), p->at<int32_t>(L.info), Q0b, ldq, p->stream));

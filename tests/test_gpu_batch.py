@@ -134,3 +134,32 @@ def test_factor_batch_limits():
         with pytest.raises(rc.RcqrError):
             p.factor_batch(V)  # more than 64 columns
     torch.cuda.synchronize()
+
+
+def test_factor_batch_members_match_oracle():
+    # members of one rcqr_factor_batch launch against the CPU oracle on their own seeds:
+    # W1 (the workspace slice of member 0 is the plan's), R to 1e-10 (kappa <= 1e6), 10 n u bounds
+    import numpy as np
+
+    from oracle.rand_cholqr import U_PAPER, rand_cholqr as oracle_rand_cholqr
+
+    for m, n, s1, s2 in [(10_000, 16, 512, 64), (20_001, 50, 5000, 200)]:
+        k, seed = 4, 90
+        print("factor_batch vs oracle:", m, n, s1, s2, flush=True)
+        Vh = [synth.make_V(m, n, 10.0 ** (3 + b), seed=seed + b) for b in range(k)]
+        V = torch.stack([torch.from_numpy(v) for v in Vh]).to("cuda")
+        with rc.Plan(m, n, s1, s2, seed=seed, batch=k) as pb:
+            Q, R = pb.factor_batch(V)
+            torch.cuda.synchronize()
+            assert pb.info_batch(k) == [(rc.OK, 0)] * k
+            W1_0 = pb.intermediates()["W1"].cpu().numpy()
+        tgt = 10 * n * U_PAPER
+        for b in range(k):
+            o = oracle_rand_cholqr(Vh[b], s1, s2, seed + b)
+            assert o["status"] == 0
+            if b == 0:
+                assert np.linalg.norm(W1_0 - o["W1"]) <= 1e-13 * np.linalg.norm(o["W1"])
+            Qb, Rb = Q[b].cpu().numpy(), R[b].cpu().numpy()
+            assert np.linalg.norm(Rb - o["R"]) <= 1e-10 * np.linalg.norm(o["R"]), b
+            assert np.linalg.norm(np.eye(n) - Qb.T @ Qb) <= tgt
+            assert np.linalg.norm(Vh[b] - Qb @ Rb) / np.linalg.norm(Vh[b]) <= tgt

@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import synth
-from oracle.rand_cholqr import U_PAPER
+from oracle.rand_cholqr import U_PAPER, rand_cholqr as oracle_rand_cholqr
 
 pytestmark = pytest.mark.gpu
 
@@ -20,6 +20,20 @@ def _gpu():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     rc.lib()
+
+
+def check_against_oracle(reqs, outputs, Vs, count):
+    """Served Q and R of up to `count` requests with kappa <= 1e6 (smallest first) against the CPU
+    oracle on the request's seed: R to 1e-10 relative, Q to 1e-10 * max(1, kappa / 1e4)."""
+    sample = sorted((r for r in reqs if r["kappa"] <= 1e6), key=lambda r: r["m"] * r["n"])[:count]
+    assert sample, "no request with kappa <= 1e6 to compare"
+    for r in sample:
+        Qs, Rs = outputs[r["seed"]]
+        Qh, Rh = Qs.cpu().numpy(), Rs.cpu().numpy()
+        o = oracle_rand_cholqr(Vs[r["seed"]].cpu().numpy(), r["s1"], r["s2"], r["seed"])
+        assert o["status"] == 0
+        assert np.linalg.norm(Rh - o["R"]) <= 1e-10 * np.linalg.norm(o["R"]), r
+        assert np.linalg.norm(Qh - o["Q"]) <= 1e-10 * max(1.0, r["kappa"] / 1e4) * np.linalg.norm(o["Q"]), r
 
 
 def test_served_results_equal_solo_results():
@@ -44,6 +58,7 @@ def test_served_results_equal_solo_results():
         tgt = 10 * n * U_PAPER
         assert np.linalg.norm(np.eye(n) - Qh.T @ Qh) <= tgt
         assert np.linalg.norm(Vh - Qh @ Rh) / np.linalg.norm(Vh) <= tgt
+    check_against_oracle(reqs, backend.outputs, Vs, 5)
 
 
 def test_memory_budget_serialises_requests():
@@ -77,6 +92,7 @@ def test_same_shape_requests_batched_equal_solo_results():
             Q, R = p.factor(Vs[r["seed"]])
         torch.cuda.synchronize()
         assert torch.equal(Q, Qs) and torch.equal(R, Rs), r
+    check_against_oracle([r for r in reqs if r["n"] <= 16], backend.outputs, Vs, 4)
 
 
 def test_reused_backend_with_plan_evictions_equals_solo_results():
