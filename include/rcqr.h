@@ -57,7 +57,8 @@ typedef enum {
   RCQR_E_NOMEM = 3,       /* host allocation of the plan failed */
   RCQR_E_HIP = 4,         /* a HIP runtime call failed (launch, event, copy) */
   RCQR_E_RANK = 5,        /* Householder R0 of the sketch has a zero / non-finite diagonal */
-  RCQR_E_CHOL = 6         /* Cholesky of the Gram matrix met a non-positive pivot */
+  RCQR_E_CHOL = 6,        /* Cholesky of the Gram matrix met a non-positive pivot */
+  RCQR_E_SCRATCH = 7      /* rcqr_factor_static: the shape's workspace exceeds the static scratch */
 } rcqr_status_t;
 
 /* Largest number of columns the kernels support. */
@@ -258,6 +259,35 @@ rcqr_status_t rcqr_info_member(rcqr_plan_t plan, int32_t member, int32_t* status
 /* Statuses of members 0 .. count-1 into host arrays status[count], column[count] with one copy
  * (synchronises the plan's stream).  RCQR_E_INVALID for count < 1 or beyond the workspace. */
 rcqr_status_t rcqr_info_batch(rcqr_plan_t plan, int32_t count, int32_t* status, int32_t* column);
+
+/*
+ * Allocation-free factorization, for callers that cannot allocate device memory: code under HIP
+ * graph capture, serving loops that must not call hipMalloc, harnesses that forbid it.  Runs
+ * exactly the kernels of rcqr_factor (same results, bit for bit) with the workspace taken from a
+ * library-owned static device array of RCQR_STATIC_WORKSPACE_BYTES (64 MiB) instead of a plan's:
+ * no plan, no hipMalloc / hipFree, no host allocation.  Each GPU the library runs on holds its own
+ * copy of the array until the process ends; its device address is looked up once per device, on
+ * the first call on that device (hipGetSymbolAddress, with the stream's device current).
+ *   m, n, s1, s2, seed, flags: as for rcqr_plan; V, Q, R: as for rcqr_factor (caller-owned device
+ *   memory; Q may alias V under rcqr_factor's rule);
+ *   d_info: NULL, or caller-owned device memory for two int32 that receive, in stream order, the
+ *   status (RCQR_OK, RCQR_E_RANK, RCQR_E_CHOL) and the 1-based failing column, as rcqr_info reports
+ *   them for a plan;
+ *   stream: a hipStream_t (NULL = the default stream); the work is enqueued there, asynchronously.
+ * Errors, returned synchronously before anything is launched: RCQR_E_INVALID / RCQR_E_UNSUPPORTED
+ * for the arguments rcqr_plan and rcqr_factor reject; RCQR_E_SCRATCH when
+ * rcqr_workspace_bytes(m, n, s1, s2, flags) exceeds RCQR_STATIC_WORKSPACE_BYTES (2,000,000 x 64 with
+ * s1 = 8192, s2 = 256 needs 48.8 MiB and fits; 128 columns with s1 = 32768 need more than 72 MiB
+ * and do not); RCQR_E_HIP.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU (two host threads,
+ * or two streams whose work is not ordered) race and give wrong results; calls ordered on one
+ * stream, or on streams ordered by events, are safe.  The array keeps the last call's contents;
+ * everything a call reads from it is written earlier in the same call.
+ */
+#define RCQR_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+rcqr_status_t rcqr_factor_static(int64_t m, int64_t n, int64_t s1, int64_t s2, uint64_t seed, uint32_t flags,
+                                 const double* d_V, int64_t ldv, double* d_Q, int64_t ldq, double* d_R, int64_t ldr,
+                                 int32_t* d_info, void* stream);
 
 /* ------------------------------------------------------------------------------------------
  * Inspection entry points (same library; used by tests, never on a timed path).

@@ -18,7 +18,8 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "librcqr.so")
 HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "rcqr.h")
 
-OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_HIP, E_RANK, E_CHOL = range(7)
+OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_HIP, E_RANK, E_CHOL, E_SCRATCH = range(8)
+STATIC_WORKSPACE_BYTES = 64 << 20  # RCQR_STATIC_WORKSPACE_BYTES: scratch of rcqr_factor_static per GPU
 MAX_N = 128  # largest number of columns the kernels accept
 # plan flags (include/rcqr.h): single-precision sketch, BF16 Gaussian product, second Cholesky QR
 FLAG_SKETCH_FP32, FLAG_GEMM_BF16, FLAG_REORTH = 1, 2, 4
@@ -59,6 +60,8 @@ _SIGNATURES = {
     "rcqr_info_member": (_c_i32, [_c_p, _c_i32, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32)]),
     "rcqr_info_batch": (_c_i32, [_c_p, _c_i32, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32)]),
     "rcqr_batch_destroy": (_c_i32, [_c_p]),
+    "rcqr_factor_static": (_c_i32, [_c_i64, _c_i64, _c_i64, _c_i64, _c_u64, _c_u32, _c_p, _c_i64, _c_p, _c_i64, _c_p, _c_i64, _c_p,
+                                    _c_p]),
 }
 
 
@@ -365,6 +368,26 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def factor_static(V, Q, R, s1, s2, seed, info=None, flags=0, stream=None):
+    """rcqr_factor_static: Algorithm 3 on V into the caller's Q and R with the library's static
+    per-GPU workspace (no plan, no device allocation by the library).  info: None or a CUDA int32
+    tensor of two entries that receives (status, failing column) in stream order.  Enqueued on
+    `stream` (default: the current stream) and not waited for."""
+    m, n = V.shape
+    _check_matrix(V, m, n, "V")
+    _check_matrix(Q, m, n, "Q")
+    _check_matrix(R, n, n, "R")
+    ip = None
+    if info is not None:
+        if not info.is_cuda or info.dtype != torch.int32 or info.numel() < 2 or not info.is_contiguous():
+            raise ValueError("info must be a contiguous CUDA int32 tensor of two entries")
+        ip = ctypes.c_void_p(info.data_ptr())
+    _check(lib().rcqr_factor_static(m, n, int(s1), int(s2), int(seed), int(flags), ctypes.c_void_p(V.data_ptr()), V.stride(0),
+                                    ctypes.c_void_p(Q.data_ptr()), Q.stride(0), ctypes.c_void_p(R.data_ptr()), R.stride(0), ip,
+                                    _stream_ptr(stream)), "rcqr_factor_static")
+    return Q, R
 
 
 def rand_cholqr(V, s1, s2, seed, check=True, flags=0):

@@ -31,6 +31,8 @@ __host__ __device__ inline T* member_ptr(T* p, int64_t bytes) {
 // members > 1: the same fill at p + b * member_words, b < members
 hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t s, int members = 1, int64_t member_words = 0);
 hipError_t launch_fill_f64(double* p, int64_t count, double value, hipStream_t s);
+// dst[i] = src[i], i < count <= 256 (one workgroup; a kernel, so it can sit in a captured graph)
+hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int count, hipStream_t s);
 // Bucket index of S1 over `nchunk` contiguous row chunks (one workgroup each):
 //   hash_hist:  codes[i] = (h(i) << 1) | signbit(i); hist[chunk][b] = rows of the chunk in bucket b
 //   colscan:    hist[chunk][b] <- rows of bucket b in earlier chunks; counts[b] = bucket size;

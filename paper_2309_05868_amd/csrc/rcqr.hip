@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "../../include/rcqr.h"
@@ -159,6 +160,43 @@ struct rcqr_plan_s {
   do {                                       \
     if ((expr) != hipSuccess) return RCQR_E_HIP; \
   } while (0)
+
+// Workspace of rcqr_factor_static: a file-scope device array, one copy per GPU.  Host code uses
+// the per-device address from hipGetSymbolAddress, never the array's name (which on the host
+// is only a handle for the symbol lookup).
+constexpr size_t kScratchBytes = RCQR_STATIC_WORKSPACE_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+char* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of the scratch array on the stream's device (looked up once per device, with
+// that device current; the caller's current device is restored).
+static rcqr_status_t scratch_address(hipStream_t stream, char** out) {
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) return RCQR_E_HIP;
+  int dev = cur;
+  if (stream != nullptr) {
+    hipDevice_t d = 0;
+    if (hipStreamGetDevice(stream, &d) != hipSuccess) return RCQR_E_HIP;
+    dev = (int)d;
+  }
+  if (dev < 0 || dev >= kMaxDevices) return RCQR_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (g_scratch_ptr[dev] == nullptr) {
+    if (dev != cur && hipSetDevice(dev) != hipSuccess) return RCQR_E_HIP;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (dev != cur && hipSetDevice(cur) != hipSuccess) return RCQR_E_HIP;
+    if (e != hipSuccess || ptr == nullptr) return RCQR_E_HIP;
+    g_scratch_ptr[dev] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return RCQR_OK;
+}
 
 static rcqr_status_t mark(rcqr_plan_t p, int i) {
   if (p->cap > 0) {
@@ -377,6 +415,7 @@ const char* rcqr_status_string(int32_t status) {
     case RCQR_E_HIP: return "HIP runtime error";
     case RCQR_E_RANK: return "sketch R0 has a zero or non-finite diagonal entry";
     case RCQR_E_CHOL: return "Cholesky of the Gram matrix met a non-positive pivot";
+    case RCQR_E_SCRATCH: return "workspace of the shape exceeds the static scratch of rcqr_factor_static";
     default: return "unknown status";
   }
 }
@@ -861,6 +900,37 @@ rcqr_status_t rcqr_batch_launch(rcqr_batch_t b) {
 rcqr_status_t rcqr_batch_destroy(rcqr_batch_t b) {
   if (b == nullptr) return RCQR_E_INVALID;
   free_batch(b);
+  return RCQR_OK;
+}
+
+rcqr_status_t rcqr_factor_static(int64_t m, int64_t n, int64_t s1, int64_t s2, uint64_t seed, uint32_t flags, const double* V,
+                                 int64_t ldv, double* Q, int64_t ldq, double* R, int64_t ldr, int32_t* d_info, void* stream) {
+  const rcqr_status_t st = check_shape(m, n, s1, s2);
+  if (st != RCQR_OK) return st;
+  if (!flags_valid(flags)) return RCQR_E_INVALID;
+  const Shape sh = make_shape(m, n, s1, s2);
+  const Layout L = make_layout(sh);
+  if (L.total > kScratchBytes) return RCQR_E_SCRATCH;
+  char* ws = nullptr;
+  const rcqr_status_t ss = scratch_address(reinterpret_cast<hipStream_t>(stream), &ws);
+  if (ss != RCQR_OK) return ss;
+  // a plan on the stack over the scratch array: rcqr_factor's launches, nothing allocated
+  rcqr_plan_s p{};
+  p.sh = sh;
+  p.L = L;
+  p.seed = seed;
+  p.flags = flags;
+  p.stream = reinterpret_cast<hipStream_t>(stream);
+  p.ws = ws;
+  p.ws_bytes = kScratchBytes;
+  p.final_mode = RCQR_FINAL_RECOMPUTE;
+  p.grid_mult = 2;
+  p.cap = 0;
+  p.recorded = 0;
+  p.ev = nullptr;
+  const rcqr_status_t sf = rcqr_factor(&p, V, ldv, Q, ldq, R, ldr);
+  if (sf != RCQR_OK) return sf;
+  if (d_info != nullptr) RCQR_TRY(launch_copy_i32(p.at<int32_t>(L.info), d_info, 2, p.stream));
   return RCQR_OK;
 }
 

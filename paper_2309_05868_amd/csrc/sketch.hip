@@ -39,6 +39,17 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream
   hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(count, 256), members), dim3(256), 0, s, p, count, value, member_words);
   return hipGetLastError();
 }
+__global__ void copy_i32_kernel(const int32_t* __restrict__ src, int32_t* __restrict__ dst, int count) {
+  const int i = threadIdx.x;
+  if (i < count) dst[i] = src[i];
+}
+
+hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (count > 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(copy_i32_kernel, dim3(1), dim3(256), 0, s, src, dst, count);
+  return hipGetLastError();
+}
 hipError_t launch_fill_f64(double* p, int64_t count, double value, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_f64_kernel, dim3(grid_for(count, 256)), dim3(256), 0, s, p, count, value);
