@@ -846,10 +846,12 @@ def main():
         "roofline": roofline,
         "tuning": tuning,
     }
+    # the timed Q (orthonormal, the workload's shape) before the comparators overwrite Q: the CPU
+    # BLAS-3 baselines are timed on it
+    Q_host = Q.cpu().numpy() if not args.no_cpu_baseline else None
     if not args.no_comparators:
         out["comparators"] = comparators(plan, V, Q, R, eye, tgt, args.comparator_steps)
     plan.close()
-    Q_host = Q.cpu().numpy() if not args.no_cpu_baseline else None
     del Q, R
     torch.cuda.empty_cache()
     if not args.no_n128:
