@@ -80,10 +80,18 @@ typedef enum {
  * RCQR_FLAG_REORTH: one more Cholesky QR after the first: Rc = R1 R0, Q1 = V Rc^{-1} by row-wise
  *   substitution, R2 = chol(Q1^T Q1), Q = Q1 R2^{-1}, R = R2 Rc (one more read of V).  Needed when
  *   kappa(Q0) is far from 1, that is with the single-precision sketch at large kappa(V).
+ * RCQR_FLAG_SKETCH_AT_PLAN: the CountSketch S1 is generated once, by rcqr_plan (enqueued on the
+ *   plan's stream), instead of in every factorization: its bucket index (each row's bucket and
+ *   sign, the rows of every bucket in ascending order) depends only on m, s1 and the seed, and
+ *   stays in the workspace.  The experiments of Section 6.1 build S1 explicitly and leave its
+ *   generation out of their timings; with this flag a plan's factorizations are timed the same
+ *   way.  Results are bitwise those of a plan without the flag.  (No effect when s1 n is small
+ *   enough for the LDS CountSketch, which hashes rows as it reads them.)  Not for batches.
  */
 #define RCQR_FLAG_SKETCH_FP32 1u
 #define RCQR_FLAG_GEMM_BF16 2u
 #define RCQR_FLAG_REORTH 4u
+#define RCQR_FLAG_SKETCH_AT_PLAN 8u
 
 /* Bytes of device workspace a plan of this shape needs (0 if the shape or the flags are
  * invalid; the flags do not change the size).  It holds the small intermediates of Algorithm 1
@@ -241,12 +249,11 @@ rcqr_status_t rcqr_batch_destroy(rcqr_batch_t batch);
  * dimension ldv), writes Q + b * stride_q and R + b * stride_r, uses the sketch seed d_seeds[b]
  * (a device array of `count` seeds, read by the kernels; or, when d_seeds is null, the plan's
  * seed + b) and the b-th slice of the workspace, which must then hold
- * count * rcqr_workspace_bytes(m, n, s1, s2, 0) bytes (the size given to rcqr_plan).  Each of
- * the eleven kernels of the factorization is launched once for the whole batch, the member
- * being a grid index, so a batch of small factorizations costs the launches of one and fills the
- * GPU with all of them.  Member b gives bitwise the Q and R of rcqr_factor on a plan with its
- * seed.  Supported for n <= 64, s2 <= 256, flags 0 and count <= 4096; otherwise
- * RCQR_E_UNSUPPORTED.
+ * count * rcqr_workspace_bytes(m, n, s1, s2, 0) bytes (the size given to rcqr_plan).  Each
+ * kernel of the factorization is launched once for the whole batch, the member being a grid
+ * index, so a batch of small factorizations costs the launches of one and fills the GPU with
+ * all of them.  Member b gives bitwise the Q and R of rcqr_factor on a plan with its seed.
+ * Supported for plans with flags 0 and count <= 4096; otherwise RCQR_E_UNSUPPORTED.
  * Strides must keep members apart (stride_v >= m * ldv, stride_q >= m * ldq, stride_r >= n * ldr;
  * Q may be V with the same leading dimension and stride); RCQR_E_INVALID otherwise, or when the
  * workspace is too small for `count`.  Statuses: rcqr_info_member(plan, b, ...) reads member b's
@@ -255,6 +262,35 @@ rcqr_status_t rcqr_batch_destroy(rcqr_batch_t batch);
 rcqr_status_t rcqr_factor_batch(rcqr_plan_t plan, int32_t count, const double* d_V, int64_t ldv, int64_t stride_v,
                                 double* d_Q, int64_t ldq, int64_t stride_q, double* d_R, int64_t ldr, int64_t stride_r,
                                 const uint64_t* d_seeds);
+
+/*
+ * Ragged batches: matrices with the plan's n, s1 and s2 but each with its own number of rows,
+ * in one set of launches (Algorithm 3 on every member).  A member names its own device buffers
+ * (V of m x n with leading dimension ldv, Q of m x n with ldq -- Q may be V with ldq == ldv --,
+ * R of n x n with ldr), its row count n <= m <= the plan's m, and its sketch seed.
+ */
+typedef struct {
+  const double* V;
+  double* Q;
+  double* R;
+  int64_t m, ldv, ldq, ldr;
+  uint64_t seed;
+} rcqr_member_t;
+/*
+ * rcqr_factor_ragged() factors members[0 .. count-1] (a host array, read during the call) on the
+ * plan's stream with every kernel launched once for the batch: the grids are sized for the
+ * plan's m and each workgroup takes its member's rows, buffers and row-count-dependent
+ * partitions (bucket-index chunks, CountSketch copies, Gram pass workgroups) from a member
+ * description the call copies into the member's workspace slice (hipMemcpy2DAsync from host
+ * memory; one copy of about 88 bytes per member).  Member b gives bitwise the Q and R of
+ * rcqr_factor on a plan of its own shape (m_b, n, s1, s2) and seed: the partitions, and so every
+ * summation order, are those of its own shape.  The workspace must hold
+ * count * rcqr_workspace_bytes(plan m, n, s1, s2, 0) bytes (slice b serves member b); statuses are
+ * read with rcqr_info_batch / rcqr_info_member as for rcqr_factor_batch.  Flags 0 and
+ * count <= 4096 (else RCQR_E_UNSUPPORTED); RCQR_E_INVALID for a null plan or array, count < 1,
+ * a workspace too small for count, or a member outside the rules above (nothing is launched then).
+ */
+rcqr_status_t rcqr_factor_ragged(rcqr_plan_t plan, int32_t count, const rcqr_member_t* members);
 rcqr_status_t rcqr_info_member(rcqr_plan_t plan, int32_t member, int32_t* status, int32_t* column);
 /* Statuses of members 0 .. count-1 into host arrays status[count], column[count] with one copy
  * (synchronises the plan's stream).  RCQR_E_INVALID for count < 1 or beyond the workspace. */
@@ -268,7 +304,8 @@ rcqr_status_t rcqr_info_batch(rcqr_plan_t plan, int32_t count, int32_t* status, 
  * no plan, no hipMalloc / hipFree, no host allocation.  Each GPU the library runs on holds its own
  * copy of the array until the process ends; its device address is looked up once per device, on
  * the first call on that device (hipGetSymbolAddress, with the stream's device current).
- *   m, n, s1, s2, seed, flags: as for rcqr_plan; V, Q, R: as for rcqr_factor (caller-owned device
+ *   m, n, s1, s2, seed, flags: as for rcqr_plan (RCQR_FLAG_SKETCH_AT_PLAN is ignored: with no
+ *   plan, the sketch is made in the call); V, Q, R: as for rcqr_factor (caller-owned device
  *   memory; Q may alias V under rcqr_factor's rule);
  *   d_info: NULL, or caller-owned device memory for two int32 that receive, in stream order, the
  *   status (RCQR_OK, RCQR_E_RANK, RCQR_E_CHOL) and the 1-based failing column, as rcqr_info reports

@@ -21,8 +21,8 @@ HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "rcqr.h")
 OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_HIP, E_RANK, E_CHOL, E_SCRATCH = range(8)
 STATIC_WORKSPACE_BYTES = 64 << 20  # RCQR_STATIC_WORKSPACE_BYTES: scratch of rcqr_factor_static per GPU
 MAX_N = 128  # largest number of columns the kernels accept
-# plan flags (include/rcqr.h): single-precision sketch, BF16 Gaussian product, second Cholesky QR
-FLAG_SKETCH_FP32, FLAG_GEMM_BF16, FLAG_REORTH = 1, 2, 4
+# plan flags (include/rcqr.h): single-precision sketch, BF16 Gaussian product, second Cholesky QR, S1 made at plan time
+FLAG_SKETCH_FP32, FLAG_GEMM_BF16, FLAG_REORTH, FLAG_SKETCH_AT_PLAN = 1, 2, 4, 8
 METHODS = {"rand_cholqr": 0, "cholqr2": 1, "scholqr3": 2}
 FINAL_RECOMPUTE, FINAL_MATERIALIZE = 0, 1
 
@@ -60,9 +60,16 @@ _SIGNATURES = {
     "rcqr_info_member": (_c_i32, [_c_p, _c_i32, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32)]),
     "rcqr_info_batch": (_c_i32, [_c_p, _c_i32, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32)]),
     "rcqr_batch_destroy": (_c_i32, [_c_p]),
+    "rcqr_factor_ragged": (_c_i32, [_c_p, _c_i32, _c_p]),
     "rcqr_factor_static": (_c_i32, [_c_i64, _c_i64, _c_i64, _c_i64, _c_u64, _c_u32, _c_p, _c_i64, _c_p, _c_i64, _c_p, _c_i64, _c_p,
                                     _c_p]),
 }
+
+
+class _RaggedMember(ctypes.Structure):
+    """rcqr_member_t of include/rcqr.h."""
+    _fields_ = [("V", _c_p), ("Q", _c_p), ("R", _c_p), ("m", _c_i64), ("ldv", _c_i64), ("ldq", _c_i64), ("ldr", _c_i64),
+                ("seed", _c_u64)]
 
 
 class RcqrError(RuntimeError):
@@ -242,6 +249,34 @@ class Plan:
                                        ctypes.c_void_p(Q.data_ptr()), Q.stride(1), Q.stride(0),
                                        ctypes.c_void_p(R.data_ptr()), R.stride(1), R.stride(0), sp), "rcqr_factor_batch")
         return Q, R
+
+    def factor_ragged(self, Vs, Qs=None, Rs=None, seeds=None):
+        """rcqr_factor_ragged: Algorithm 3 on matrices of the plan's n, s1, s2 and their own row
+        counts (each at most the plan's m), in one set of launches.  Vs: list of CUDA float64
+        row-major tensors; Qs / Rs: outputs (allocated when None; Q may be V); seeds: one int per
+        member (default: the plan's seed + b).  Returns (Qs, Rs); statuses via info_batch."""
+        k = len(Vs)
+        if k < 1 or k > self.batch:
+            raise ValueError(f"need 1 .. {self.batch} members (the plan's batch)")
+        Qs = list(Qs) if Qs is not None else [None] * k
+        Rs = list(Rs) if Rs is not None else [None] * k
+        seeds = list(seeds) if seeds is not None else [self.seed + b for b in range(k)]
+        table = (_RaggedMember * k)()
+        for b in range(k):
+            V = Vs[b]
+            m = V.shape[0] if V.dim() == 2 else -1
+            _check_matrix(V, m, self.n, f"V[{b}]")
+            if Qs[b] is None:
+                Qs[b] = torch.empty((m, self.n), dtype=torch.float64, device=V.device)
+            if Rs[b] is None:
+                Rs[b] = torch.empty((self.n, self.n), dtype=torch.float64, device=V.device)
+            _check_matrix(Qs[b], m, self.n, f"Q[{b}]")
+            _check_matrix(Rs[b], self.n, self.n, f"R[{b}]")
+            table[b] = _RaggedMember(V.data_ptr(), Qs[b].data_ptr(), Rs[b].data_ptr(), m, V.stride(0), Qs[b].stride(0),
+                                     Rs[b].stride(0), int(seeds[b]) & 0xFFFFFFFFFFFFFFFF)
+        _check(lib().rcqr_factor_ragged(self._h, k, table), "rcqr_factor_ragged")
+        self._ragged_keep = (Vs, Qs, Rs)  # the buffers stay referenced until the next call
+        return Qs, Rs
 
     def info_batch(self, count):
         """[(status, column)] of members 0 .. count-1, one device-to-host copy."""

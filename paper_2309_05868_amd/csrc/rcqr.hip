@@ -31,7 +31,7 @@ int padded_cols(int64_t n) {
 }
 
 struct Layout {
-  size_t info, w1, csparts, codes, counts, offsets, hist, entries, unsorted, wpart, w, qra, qrb, r0, r0pk, gpart, gc, g, r1, r1pk,
+  size_t info, minfo, w1, csparts, codes, counts, offsets, hist, entries, unsorted, wpart, w, qra, qrb, r0, r0pk, gpart, gc, g, r1, r1pk,
       ra, rapk, rtmp, rtmp2, total;
 };
 
@@ -54,12 +54,7 @@ Shape make_shape(int64_t m, int64_t n, int64_t s1, int64_t s2) {
   sh.np = padded_cols(n);
   sh.lds_cs = countsketch_lds_fits(s1, (int)n);
   sh.cs_parts = sh.lds_cs ? countsketch_lds_parts(m, s1, (int)n) : 0;
-  // bucket index: chunks of at least 4096 rows, at most 256, histogram matrix <= 2^26 entries
-  int64_t nch = (m + 4095) / 4096;
-  if (nch > 256) nch = 256;
-  const int64_t cap_ch = ((int64_t)1 << 26) / s1;
-  if (nch > cap_ch) nch = cap_ch;
-  sh.nchunk = nch < 1 ? 1 : (int)nch;
+  sh.nchunk = bucket_nchunk(m, s1);
   // Gaussian GEMM split over s1: about 512 workgroups, partials capped at 16 MiB
   const int64_t nrb = (s2 + 63) / 64;
   int64_t nkc = 512 / nrb;
@@ -86,6 +81,7 @@ Layout make_layout(const Shape& sh) {
   };
   const size_t n = (size_t)sh.n, np = (size_t)sh.np;
   L.info = take(16 * sizeof(int32_t));
+  L.minfo = take(sizeof(MemberInfo));  // a ragged batch's member description
   L.w1 = take((size_t)sh.s1 * n * 8);
   L.csparts = take(sh.lds_cs ? (size_t)sh.cs_parts * sh.s1 * n * 8 : 0);
   const size_t mm = sh.lds_cs ? 0 : (size_t)sh.m;
@@ -124,7 +120,7 @@ rcqr_status_t check_shape(int64_t m, int64_t n, int64_t s1, int64_t s2) {
 }
 
 bool flags_valid(uint32_t flags) {
-  const uint32_t known = RCQR_FLAG_SKETCH_FP32 | RCQR_FLAG_GEMM_BF16 | RCQR_FLAG_REORTH;
+  const uint32_t known = RCQR_FLAG_SKETCH_FP32 | RCQR_FLAG_GEMM_BF16 | RCQR_FLAG_REORTH | RCQR_FLAG_SKETCH_AT_PLAN;
   if (flags & ~known) return false;
   if ((flags & RCQR_FLAG_GEMM_BF16) && !(flags & RCQR_FLAG_SKETCH_FP32)) return false;
   return true;
@@ -149,6 +145,9 @@ struct rcqr_plan_s {
   int cap;
   int recorded;
   hipEvent_t* ev;
+  // host staging of a ragged batch's member descriptions (copied into the workspace slices)
+  MemberInfo* staged;
+  int32_t staged_cap;
 
   template <class T>
   T* at(size_t off) const {
@@ -242,6 +241,25 @@ static rcqr_status_t run_householder(rcqr_plan_t p) {
   return RCQR_OK;
 }
 
+// The CountSketch S1 (Section 3) as a bucket index: each row's bucket and sign, then the rows of
+// every bucket listed in ascending order.  A function of (m, s1, seed) only.
+static rcqr_status_t build_bucket_index(rcqr_plan_t p) {
+  const Shape& sh = p->sh;
+  const Layout& L = p->L;
+  hipStream_t s = p->stream;
+  uint32_t* counts = p->at<uint32_t>(L.counts);
+  uint32_t* offsets = p->at<uint32_t>(L.offsets);
+  uint32_t* hist = p->at<uint32_t>(L.hist);
+  uint32_t* codes = p->at<uint32_t>(L.codes);
+  uint32_t* entries = p->at<uint32_t>(L.entries);
+  uint8_t* unsorted = p->at<uint8_t>(L.unsorted);
+  RCQR_TRY(launch_hash_hist(sh.m, sh.s1, p->seed, sh.nchunk, codes, hist, s));
+  RCQR_TRY(launch_hist_colscan(sh.nchunk, sh.s1, hist, counts, unsorted, s));
+  RCQR_TRY(launch_bucket_scan(counts, sh.s1, offsets, nullptr, s));
+  RCQR_TRY(launch_bucket_scatter(sh.m, sh.s1, sh.nchunk, codes, offsets, hist, entries, unsorted, s));
+  return RCQR_OK;
+}
+
 // Algorithm 1, step 1: W1 = S1 V, then W = S2 W1, in FP64 or (single-precision sketch) FP32.
 template <class T>
 static rcqr_status_t run_sketch(rcqr_plan_t p, const double* V, int64_t ldv) {
@@ -255,17 +273,10 @@ static rcqr_status_t run_sketch(rcqr_plan_t p, const double* V, int64_t ldv) {
     RCQR_TRY(launch_countsketch_lds(V, ldv, sh.m, n, sh.s1, p->seed, parts, sh.cs_parts, s));
     RCQR_TRY(launch_reduce_parts(parts, sh.cs_parts, sh.s1 * sh.n, sh.s1 * sh.n, W1, s));
   } else {
-    uint32_t* counts = p->at<uint32_t>(L.counts);
-    uint32_t* offsets = p->at<uint32_t>(L.offsets);
-    uint32_t* hist = p->at<uint32_t>(L.hist);
-    uint32_t* codes = p->at<uint32_t>(L.codes);
-    uint32_t* entries = p->at<uint32_t>(L.entries);
-    RCQR_TRY(launch_hash_hist(sh.m, sh.s1, p->seed, sh.nchunk, codes, hist, s));
-    uint8_t* unsorted = p->at<uint8_t>(L.unsorted);
-    RCQR_TRY(launch_hist_colscan(sh.nchunk, sh.s1, hist, counts, unsorted, s));
-    RCQR_TRY(launch_bucket_scan(counts, sh.s1, offsets, nullptr, s));
-    RCQR_TRY(launch_bucket_scatter(sh.m, sh.s1, sh.nchunk, codes, offsets, hist, entries, unsorted, s));
-    RCQR_TRY(launch_bucket_gather(V, ldv, sh.m, n, sh.s1, offsets, entries, bucket_scatter_sorts(sh.s1) ? unsorted : nullptr, W1, s));
+    if (!(p->flags & RCQR_FLAG_SKETCH_AT_PLAN) && build_bucket_index(p) != RCQR_OK) return RCQR_E_HIP;
+    const uint8_t* unsorted = p->at<uint8_t>(L.unsorted);
+    RCQR_TRY(launch_bucket_gather(V, ldv, sh.m, n, sh.s1, p->at<uint32_t>(L.offsets), p->at<uint32_t>(L.entries),
+                                  bucket_scatter_sorts(sh.s1) ? unsorted : nullptr, W1, s));
   }
   if (mark(p, 1) != RCQR_OK) return RCQR_E_HIP;
   const double scale = 1.0 / std::sqrt((double)sh.s2);
@@ -356,6 +367,12 @@ rcqr_status_t rcqr_plan(rcqr_plan_t* plan, int64_t m, int64_t n, int64_t s1, int
   p->cap = 0;
   p->recorded = 0;
   p->ev = nullptr;
+  p->staged = nullptr;
+  p->staged_cap = 0;
+  if ((flags & RCQR_FLAG_SKETCH_AT_PLAN) && !sh.lds_cs && build_bucket_index(p) != RCQR_OK) {
+    delete p;
+    return RCQR_E_HIP;
+  }
   *plan = p;
   return RCQR_OK;
 }
@@ -363,6 +380,7 @@ rcqr_status_t rcqr_plan(rcqr_plan_t* plan, int64_t m, int64_t n, int64_t s1, int
 rcqr_status_t rcqr_destroy(rcqr_plan_t p) {
   if (p == nullptr) return RCQR_E_INVALID;
   free_events(p);
+  delete[] p->staged;
   delete p;
   return RCQR_OK;
 }
@@ -481,32 +499,22 @@ rcqr_status_t rcqr_factor(rcqr_plan_t p, const double* V, int64_t ldv, double* Q
   return RCQR_OK;
 }
 
-rcqr_status_t rcqr_factor_batch(rcqr_plan_t p, int32_t count, const double* V, int64_t ldv, int64_t sv, double* Q, int64_t ldq,
-                                int64_t sq, double* R, int64_t ldr, int64_t sr, const uint64_t* d_seeds) {
-  const rcqr_status_t st = check_io(p, V, ldv, Q, ldq, R, ldr);
-  if (st != RCQR_OK) return st;
+// Algorithm 3 on a batch (every kernel launched once for all members; see MemberStride): the
+// steps of rcqr_factor in FP64, members of the plan's n, s1 and s2.
+static rcqr_status_t run_batch(rcqr_plan_t p, const MemberStride& ms, const double* V, int64_t ldv, double* Q, int64_t ldq, double* R,
+                               int64_t ldr) {
   const Shape& sh = p->sh;
   const Layout& L = p->L;
-  if (count < 1 || (size_t)count > p->ws_bytes / L.total) return RCQR_E_INVALID;
-  // members must not overlap (Q may be V itself, member by member)
-  if (sv < sh.m * ldv || sq < sh.m * ldq || sr < sh.n * ldr) return RCQR_E_INVALID;
-  if ((const void*)Q == (const void*)V && sq != sv) return RCQR_E_INVALID;
-  if (sh.np > 64 || sh.s2 > kQrRows || p->flags != 0 || count > kMaxBatch) return RCQR_E_UNSUPPORTED;
   const int n = (int)sh.n;
+  const int count = ms.count;
   hipStream_t s = p->stream;
-  MemberStride ms;
-  ms.ws = (int64_t)L.total;
-  ms.v = sv;
-  ms.q = sq;
-  ms.r = sr;
-  ms.count = count;
-  ms.seeds = d_seeds;
   int32_t* info = p->at<int32_t>(L.info);
-  // the steps of rcqr_factor on the small-sketch FP64 path, each one launch for all members
   RCQR_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(info), 16, 0u, s, count, ms.ws / 4));
+  // Algorithm 1, step 1: W1 = S1 V, W = S2 W1
   if (sh.lds_cs) {
     RCQR_TRY(launch_countsketch_lds(V, ldv, sh.m, n, sh.s1, p->seed, p->at<double>(L.csparts), sh.cs_parts, s, ms));
-    RCQR_TRY(launch_reduce_parts(p->at<double>(L.csparts), sh.cs_parts, sh.s1 * sh.n, sh.s1 * sh.n, p->at<double>(L.w1), s, ms));
+    RCQR_TRY(launch_reduce_parts(p->at<double>(L.csparts), sh.cs_parts, sh.s1 * sh.n, sh.s1 * sh.n, p->at<double>(L.w1), s, ms,
+                                 kPartsCountSketch));
   } else {
     uint32_t* counts = p->at<uint32_t>(L.counts);
     uint32_t* offsets = p->at<uint32_t>(L.offsets);
@@ -524,15 +532,113 @@ rcqr_status_t rcqr_factor_batch(rcqr_plan_t p, int32_t count, const double* V, i
   const double scale = 1.0 / std::sqrt((double)sh.s2);
   RCQR_TRY(launch_gauss_gemm(p->at<double>(L.w1), n, sh.s1, sh.s2, p->seed, scale, sh.kc_len, sh.nkc, p->at<double>(L.wpart), s, ms));
   RCQR_TRY(launch_reduce_parts(p->at<double>(L.wpart), sh.nkc, sh.s2 * sh.n, sh.s2 * sh.n, p->at<double>(L.w), s, ms));
-  RCQR_TRY(launch_qr_blocks(p->at<double>(L.w), n, sh.s2, kQrRows, n, p->at<double>(L.qra), 1, s, ms));
-  RCQR_TRY(launch_finalize_r0(p->at<double>(L.qra), n, sh.np, info, p->at<double>(L.r0), p->at<double>(L.r0pk), s, ms));
-  RCQR_TRY(launch_trsm_gram(sh.np, V, sh.m, n, ldv, p->at<double>(L.r0pk), info, p->at<double>(L.gpart), nullptr, ldq, s, ms));
+  // Algorithm 1, step 2: R0 = hhqr(W), the TSQR levels of run_householder
+  {
+    const double* in = p->at<double>(L.w);
+    int64_t rows = sh.s2, rpb = kQrRows;
+    double* bufs[2] = {p->at<double>(L.qra), p->at<double>(L.qrb)};
+    int which = 0;
+    for (;;) {
+      const int64_t nblocks = (rows + rpb - 1) / rpb;
+      RCQR_TRY(launch_qr_blocks(in, n, rows, rpb, n, bufs[which], (int)nblocks, s, ms));
+      in = bufs[which];
+      which ^= 1;
+      if (nblocks == 1) break;
+      rows = nblocks * n;
+      rpb = (kQrRows / n) * n;
+    }
+    RCQR_TRY(launch_finalize_r0(in, n, sh.np, info, p->at<double>(L.r0), p->at<double>(L.r0pk), s, ms));
+  }
+  // Algorithm 1, step 3 + Algorithm 2, step 1: G = Q0^T Q0 (Q0 stored in Q above 64 columns)
   const int64_t len = gram_compact_len(sh.np);
-  RCQR_TRY(launch_reduce_parts(p->at<double>(L.gpart), gram_blocks(sh.m), len, len, p->at<double>(L.gc), s, ms));
+  if (sh.np <= 64) {
+    RCQR_TRY(launch_trsm_gram(sh.np, V, sh.m, n, ldv, p->at<double>(L.r0pk), info, p->at<double>(L.gpart), nullptr, ldq, s, ms));
+    RCQR_TRY(launch_reduce_parts(p->at<double>(L.gpart), gram_blocks(sh.m), len, len, p->at<double>(L.gc), s, ms, kPartsGram));
+  } else {
+    RCQR_TRY(launch_solve128(V, sh.m, n, ldv, p->at<double>(L.r0pk), info, Q, ldq, s, p->grid_mult, ms, 0));
+    RCQR_TRY(launch_syrk128(Q, sh.m, n, ldq, info, p->at<double>(L.gpart), s, ms));
+    RCQR_TRY(launch_reduce_parts(p->at<double>(L.gpart), kGramBlocks, len, len, p->at<double>(L.gc), s, ms));
+  }
+  // Algorithm 2, step 2 and Algorithm 3, step 3: R1 = chol(G), R = R1 R0
   RCQR_TRY(launch_cholesky(p->at<double>(L.gc), n, sh.np, p->at<double>(L.r0), 0.0, info, p->at<double>(L.g), p->at<double>(L.r1),
                            p->at<double>(L.r1pk), R, ldr, s, ms));
-  RCQR_TRY(launch_final(sh.np, true, V, sh.m, n, ldv, p->at<double>(L.r0pk), p->at<double>(L.r1pk), info, Q, ldq, s, p->grid_mult, ms));
+  // Algorithm 2, step 3 on Q0: Q = Q0 R1^{-1}
+  if (sh.np <= 64) {
+    RCQR_TRY(launch_final(sh.np, true, V, sh.m, n, ldv, p->at<double>(L.r0pk), p->at<double>(L.r1pk), info, Q, ldq, s, p->grid_mult, ms));
+  } else {
+    RCQR_TRY(launch_solve128(Q, sh.m, n, ldq, p->at<double>(L.r1pk), info, Q, ldq, s, p->grid_mult, ms, 1));
+  }
   return RCQR_OK;
+}
+
+rcqr_status_t rcqr_factor_batch(rcqr_plan_t p, int32_t count, const double* V, int64_t ldv, int64_t sv, double* Q, int64_t ldq,
+                                int64_t sq, double* R, int64_t ldr, int64_t sr, const uint64_t* d_seeds) {
+  const rcqr_status_t st = check_io(p, V, ldv, Q, ldq, R, ldr);
+  if (st != RCQR_OK) return st;
+  const Shape& sh = p->sh;
+  const Layout& L = p->L;
+  if (count < 1 || (size_t)count > p->ws_bytes / L.total) return RCQR_E_INVALID;
+  // members must not overlap (Q may be V itself, member by member)
+  if (sv < sh.m * ldv || sq < sh.m * ldq || sr < sh.n * ldr) return RCQR_E_INVALID;
+  if ((const void*)Q == (const void*)V && sq != sv) return RCQR_E_INVALID;
+  if (p->flags != 0 || count > kMaxBatch) return RCQR_E_UNSUPPORTED;
+  MemberStride ms;
+  ms.ws = (int64_t)L.total;
+  ms.v = sv;
+  ms.q = sq;
+  ms.r = sr;
+  ms.count = count;
+  ms.seeds = d_seeds;
+  return run_batch(p, ms, V, ldv, Q, ldq, R, ldr);
+}
+
+static bool rows_aligned(const void* a, int64_t ld) { return (reinterpret_cast<uintptr_t>(a) % 16 == 0) && (ld % 2 == 0); }
+
+rcqr_status_t rcqr_factor_ragged(rcqr_plan_t p, int32_t count, const rcqr_member_t* members) {
+  if (p == nullptr || members == nullptr || count < 1) return RCQR_E_INVALID;
+  const Shape& sh = p->sh;
+  const Layout& L = p->L;
+  if ((size_t)count > p->ws_bytes / L.total) return RCQR_E_INVALID;
+  if (p->flags != 0 || count > kMaxBatch) return RCQR_E_UNSUPPORTED;
+  if (p->staged_cap < count) {
+    MemberInfo* fresh = new (std::nothrow) MemberInfo[count];
+    if (fresh == nullptr) return RCQR_E_NOMEM;
+    delete[] p->staged;
+    p->staged = fresh;
+    p->staged_cap = count;
+  }
+  bool aligned = true;
+  for (int32_t b = 0; b < count; ++b) {
+    const rcqr_member_t& r = members[b];
+    if (r.V == nullptr || r.Q == nullptr || r.R == nullptr || r.m < sh.n || r.m > sh.m) return RCQR_E_INVALID;
+    if (r.ldv < sh.n || r.ldq < sh.n || r.ldr < sh.n) return RCQR_E_INVALID;
+    if ((const void*)r.Q == (const void*)r.V && r.ldq != r.ldv) return RCQR_E_INVALID;
+    MemberInfo& mi = p->staged[b];
+    mi.V = r.V;
+    mi.Q = r.Q;
+    mi.R = r.R;
+    mi.m = r.m;
+    mi.ldv = r.ldv;
+    mi.ldq = r.ldq;
+    mi.ldr = r.ldr;
+    mi.seed = r.seed;
+    mi.nchunk = bucket_nchunk(r.m, sh.s1);
+    mi.chunk_rows = bucket_chunk_rows(r.m, mi.nchunk);
+    mi.cs_parts = sh.lds_cs ? countsketch_lds_parts(r.m, sh.s1, (int)sh.n) : 0;
+    mi.gblocks = gram_blocks(r.m);
+    mi.pad = 0;
+    aligned = aligned && rows_aligned(r.V, r.ldv) && rows_aligned(r.Q, r.ldq);
+  }
+  // the member descriptions into their workspace slices (one strided copy), then the batch
+  RCQR_TRY(hipMemcpy2DAsync(p->ws + L.minfo, L.total, p->staged, sizeof(MemberInfo), sizeof(MemberInfo), (size_t)count,
+                            hipMemcpyHostToDevice, p->stream));
+  MemberStride ms;
+  ms.ws = (int64_t)L.total;
+  ms.count = count;
+  ms.info = p->at<MemberInfo>(L.minfo);
+  ms.aligned = aligned;
+  // V, Q, R below only size the launches (every kernel takes its member's from the table)
+  return run_batch(p, ms, members[0].V, members[0].ldv, members[0].Q, members[0].ldq, members[0].R, members[0].ldr);
 }
 
 rcqr_status_t rcqr_info_member(rcqr_plan_t p, int32_t member, int32_t* status, int32_t* column) {
@@ -919,7 +1025,7 @@ rcqr_status_t rcqr_factor_static(int64_t m, int64_t n, int64_t s1, int64_t s2, u
   p.sh = sh;
   p.L = L;
   p.seed = seed;
-  p.flags = flags;
+  p.flags = flags & ~RCQR_FLAG_SKETCH_AT_PLAN;  // no plan outlives the call: the sketch is made in it
   p.stream = reinterpret_cast<hipStream_t>(stream);
   p.ws = ws;
   p.ws_bytes = kScratchBytes;

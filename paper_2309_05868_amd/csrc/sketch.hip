@@ -63,8 +63,6 @@ hipError_t launch_fill_f64(double* p, int64_t count, double value, hipStream_t s
 // ------------------------------------------------------------------------------------------
 constexpr int kHistLds = 16384;  // buckets counted in LDS; above this, in the chunk's global row
 
-int64_t bucket_chunk_rows(int64_t m, int nchunk) { return ((m + nchunk - 1) / nchunk + 3) / 4 * 4; }
-
 __global__ __launch_bounds__(256) void hash_hist_kernel(int64_t m, uint64_t s1, uint64_t seed, int64_t chunk_rows, uint32_t* __restrict__ codes,
                                                         uint32_t* __restrict__ hist, MemberStride ms) {
   __shared__ uint32_t lh[kHistLds];
@@ -73,6 +71,12 @@ __global__ __launch_bounds__(256) void hash_hist_kernel(int64_t m, uint64_t s1, 
     codes = member_ptr(codes, mb * ms.ws);
     hist = member_ptr(hist, mb * ms.ws);
     seed = member_seed(seed, ms, mb);
+    if (ms.info != nullptr) {  // ragged batch: the member's rows and chunks
+      const MemberInfo& mi = member_info(ms, mb);
+      if ((int)blockIdx.x >= mi.nchunk) return;
+      m = mi.m;
+      chunk_rows = mi.chunk_rows;
+    }
   }
   const bool in_lds = s1 <= (uint64_t)kHistLds;
   uint32_t* gh = hist + (int64_t)blockIdx.x * (int64_t)s1;
@@ -119,13 +123,14 @@ hipError_t launch_hash_hist(int64_t m, int64_t s1, uint64_t seed, int nchunk, ui
 // counts[b] <- total rows of bucket b.  Workgroup: 32 buckets x 8 chunk segments; each thread
 // scans its segment of one column, the segment totals are combined through LDS.
 __global__ __launch_bounds__(256) void hist_colscan_kernel(int nchunk, int64_t s1, uint32_t* __restrict__ hist, uint32_t* __restrict__ counts,
-                                                           uint8_t* __restrict__ unsorted, int64_t member_bytes) {
+                                                           uint8_t* __restrict__ unsorted, MemberStride ms) {
   constexpr int NB = 32, NS = 8, BATCH = 8;
   {
-    const int64_t off = (int64_t)blockIdx.y * member_bytes;  // batch member
+    const int64_t off = (int64_t)blockIdx.y * ms.ws;  // batch member
     hist = member_ptr(hist, off);
     counts = member_ptr(counts, off);
     unsorted = member_ptr(unsorted, off);
+    if (ms.info != nullptr) nchunk = member_info(ms, blockIdx.y).nchunk;
   }
   __shared__ uint32_t segtot[NS][NB];
   const int bl = threadIdx.x % NB, sg = threadIdx.x / NB;
@@ -168,7 +173,7 @@ hipError_t launch_hist_colscan(int nchunk, int64_t s1, uint32_t* hist, uint32_t*
                                const MemberStride& ms) {
   if (ms.count < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(hist_colscan_kernel, dim3((unsigned)((s1 + 31) / 32), ms.count), dim3(256), 0, s, nchunk, s1, hist, counts, unsorted,
-                     ms.ws);
+                     ms);
   return hipGetLastError();
 }
 
@@ -290,15 +295,21 @@ bool bucket_scatter_sorts(int64_t s1) { return s1 <= (int64_t)kHistLds; }
 // segments are left as they are and the gather sorts every bucket.
 __global__ __launch_bounds__(256) void bucket_scatter_kernel(int64_t m, int64_t s1, int64_t chunk_rows, const uint32_t* __restrict__ codes,
                                                              const uint32_t* __restrict__ offsets, uint32_t* __restrict__ hist,
-                                                             uint32_t* entries, uint8_t* __restrict__ unsorted, int64_t member_bytes) {
+                                                             uint32_t* entries, uint8_t* __restrict__ unsorted, MemberStride ms) {
   __shared__ uint32_t cur[kHistLds];
   {
-    const int64_t off = (int64_t)blockIdx.y * member_bytes;  // batch member
+    const int64_t off = (int64_t)blockIdx.y * ms.ws;  // batch member
     codes = member_ptr(codes, off);
     offsets = member_ptr(offsets, off);
     hist = member_ptr(hist, off);
     entries = member_ptr(entries, off);
     unsorted = member_ptr(unsorted, off);
+    if (ms.info != nullptr) {  // ragged batch: the member's rows and chunks
+      const MemberInfo& mi = member_info(ms, blockIdx.y);
+      if ((int)blockIdx.x >= mi.nchunk) return;
+      m = mi.m;
+      chunk_rows = mi.chunk_rows;
+    }
   }
   __shared__ uint32_t seg0[kHistLds];  // start of this chunk's segment of each bucket
   const bool in_lds = s1 <= (int64_t)kHistLds;
@@ -346,7 +357,7 @@ hipError_t launch_bucket_scatter(int64_t m, int64_t s1, int nchunk, const uint32
   if (m <= 0) return hipSuccess;
   if ((bucket_scatter_sorts(s1) && unsorted == nullptr) || ms.count < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(bucket_scatter_kernel, dim3(nchunk, ms.count), dim3(256), 0, s, m, s1, bucket_chunk_rows(m, nchunk), codes, offsets,
-                     hist, entries, unsorted, ms.ws);
+                     hist, entries, unsorted, ms);
   return hipGetLastError();
 }
 
@@ -439,7 +450,7 @@ __global__ __launch_bounds__(256) void bucket_gather_kernel(const double* __rest
   __shared__ uint32_t keys_all[kGatherWaves][kSortCap];
   {
     const int64_t mb = blockIdx.y, off = mb * ms.ws;  // batch member
-    V += mb * ms.v;
+    member_v(ms, mb, V, m, ldv);
     offsets = member_ptr(offsets, off);
     entries = member_ptr(entries, off);
     unsorted = member_ptr(unsorted, off);
@@ -561,44 +572,19 @@ hipError_t launch_bucket_gather(const double* V, int64_t ldv, int64_t m, int n, 
 // ------------------------------------------------------------------------------------------
 // Small-s1 CountSketch: per-wave LDS copies of W1 (s1 x NPL), contiguous row chunks.
 // ------------------------------------------------------------------------------------------
-constexpr int kCsLdsDoubles = 4096;  // s1 * NPL limit (4 waves x 32 KiB)
-constexpr int kCsChunk = 256;         // rows hashed at once by one wave
-
-static int npl_of(int n) {
-  int p = 8;
-  while (p < n) p <<= 1;
-  return p;
-}
-
-bool countsketch_lds_fits(int64_t s1, int n) { return n <= 64 && s1 * npl_of(n) <= kCsLdsDoubles; }
-
-// Per-wave capacity of the LDS copies (elements): the smallest of 1024, 2048, 4096 that holds
-// s1 x NPL; smaller copies let more workgroups share a CU (4, 2, 1 at FP64).
-static int cs_cap(int64_t s1, int n) {
-  const int64_t need = s1 * npl_of(n);
-  return need <= 1024 ? 1024 : need <= 2048 ? 2048 : 4096;
-}
-
-// Workgroups (and partial copies of W1): one per 256-row chunk, at most 256 x (workgroups per
-// CU at FP64).  A function of the shape only, so the summation order does not depend on the device.
-int countsketch_lds_parts(int64_t m, int64_t s1, int n) {
-  const int cap = cs_cap(s1, n);
-  const int64_t target = 256 * (cap == 1024 ? 4 : cap == 2048 ? 2 : 1);
-  int64_t p = (m + kCsChunk - 1) / kCsChunk;
-  if (p > target) p = target;
-  return p < 1 ? 1 : (int)p;
-}
-
 template <int NPL, class T, int CAP>
 __global__ __launch_bounds__(256) void countsketch_lds_kernel(const double* __restrict__ V, int64_t ldv, int64_t m, int n, int64_t s1,
                                                               uint64_t seed, T* __restrict__ parts, MemberStride ms) {
   __shared__ T w1[4][CAP];
   {
     const int64_t mb = blockIdx.y;  // batch member
-    V += mb * ms.v;
+    member_v(ms, mb, V, m, ldv);
     parts = member_ptr(parts, mb * ms.ws);
     seed = member_seed(seed, ms, mb);
   }
+  // workgroups of this member (the grid is sized for the largest member of a ragged batch)
+  const int64_t nparts = ms.info != nullptr ? member_info(ms, blockIdx.y).cs_parts : (int64_t)gridDim.x;
+  if ((int64_t)blockIdx.x >= nparts) return;
   __shared__ uint32_t codes[4][kCsChunk];
   constexpr int RB = kWave / NPL;  // rows per batch
   const int wave = threadIdx.x / kWave, lane = lane_id();
@@ -606,7 +592,7 @@ __global__ __launch_bounds__(256) void countsketch_lds_kernel(const double* __re
   T* mine = w1[wave];
   for (int i = lane; i < s1 * NPL; i += kWave) mine[i] = T(0);
   // rows of this workgroup
-  const int64_t per = ((m + gridDim.x - 1) / gridDim.x + kCsChunk - 1) / kCsChunk * kCsChunk;
+  const int64_t per = ((m + nparts - 1) / nparts + kCsChunk - 1) / kCsChunk * kCsChunk;
   const int64_t r_beg = (int64_t)blockIdx.x * per;
   const int64_t r_end = r_beg + per < m ? r_beg + per : m;
   wave_lds_sync();
@@ -964,10 +950,14 @@ hipError_t launch_gaussian_block(int64_t j0, int64_t nj, int64_t k0, int64_t nk,
 // depends only on nparts, so the order of every sum is fixed.
 template <class T>
 __global__ __launch_bounds__(256) void reduce_parts_kernel(const T* __restrict__ parts, int64_t nparts, int64_t stride, int64_t len,
-                                                           T* __restrict__ out, int64_t member_bytes) {
+                                                           T* __restrict__ out, MemberStride ms, int parts_kind) {
   constexpr int E = 16, G = 16;
-  parts = member_ptr(parts, (int64_t)blockIdx.y * member_bytes);
-  out = member_ptr(out, (int64_t)blockIdx.y * member_bytes);
+  parts = member_ptr(parts, (int64_t)blockIdx.y * ms.ws);
+  out = member_ptr(out, (int64_t)blockIdx.y * ms.ws);
+  if (ms.info != nullptr && parts_kind != kPartsUniform) {  // ragged batch: the member's own partial count
+    const MemberInfo& mi = member_info(ms, blockIdx.y);
+    nparts = parts_kind == kPartsCountSketch ? mi.cs_parts : mi.gblocks;
+  }
   __shared__ T ssum[G][E], scomp[G][E];
   const int e = threadIdx.x % E, g = threadIdx.x / E;
   const int64_t i = (int64_t)blockIdx.x * E + e;
@@ -1009,17 +999,17 @@ __global__ __launch_bounds__(256) void reduce_parts_kernel(const T* __restrict__
 }
 
 hipError_t launch_reduce_parts(const double* parts, int64_t nparts, int64_t stride, int64_t len, double* out, hipStream_t s,
-                               const MemberStride& ms) {
+                               const MemberStride& ms, int parts_kind) {
   if (len <= 0 || ms.count < 1) return hipSuccess;
   hipLaunchKernelGGL(reduce_parts_kernel<double>, dim3((unsigned)((len + 15) / 16), ms.count), dim3(256), 0, s, parts, nparts, stride, len,
-                     out, ms.ws);
+                     out, ms, parts_kind);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_parts(const float* parts, int64_t nparts, int64_t stride, int64_t len, float* out, hipStream_t s) {
   if (len <= 0) return hipSuccess;
   hipLaunchKernelGGL(reduce_parts_kernel<float>, dim3((unsigned)((len + 15) / 16)), dim3(256), 0, s, parts, nparts, stride, len, out,
-                     (int64_t)0);
+                     MemberStride(), (int)kPartsUniform);
   return hipGetLastError();
 }
 

@@ -340,7 +340,13 @@ __global__ __launch_bounds__(CholShape<NP>::NWV * kWave) void cholesky_kernel(co
     g_out = member_ptr(g_out, off);
     r1 = member_ptr(r1, off);
     r1pk = member_ptr(r1pk, off);
-    r_out += mb * ms.r;
+    if (ms.info != nullptr) {  // ragged batch: the member's own R
+      const MemberInfo& mi = member_info(ms, mb);
+      r_out = mi.R;
+      ldr = mi.ldr;
+    } else {
+      r_out += mb * ms.r;
+    }
   }
   constexpr int NB = NP / 16;
   extern __shared__ double Rl[];  // NP x NP, the rows of the LDL^T elimination; then Rprev (NP <= 64)

@@ -135,15 +135,26 @@ __global__ __launch_bounds__(kGramThreads, 1) void trsm_gram_kernel(const double
   constexpr int NB = NP / 16;
   constexpr int NBU = NB * (NB + 1) / 2;
   constexpr int NW = kGramThreads / kWave;
+  int64_t nblk = gridDim.x;  // workgroups of this member
   if constexpr (BATCH) {
     // batch member: workspace pointers move by whole doubles / ints (the workspace stride is a
     // multiple of 256 bytes), keeping them typed so the factor still streams through scalar loads
     const int64_t mb = blockIdx.y, off = mb * ms.ws;
-    V += mb * ms.v;
+    member_v(ms, mb, V, m, ldv);
     R0pk += off / (int64_t)sizeof(double);
     info += off / (int64_t)sizeof(int32_t);
     gpart += off / (int64_t)sizeof(double);
-    if (q0 != nullptr) q0 += mb * ms.q;
+    if (ms.info != nullptr) {  // ragged batch: the member's own Gram grid and Q
+      const MemberInfo& mi = member_info(ms, mb);
+      nblk = mi.gblocks;
+      if (q0 != nullptr) {
+        q0 = mi.Q;
+        ldq = mi.ldq;
+      }
+    } else if (q0 != nullptr) {
+      q0 += mb * ms.q;
+    }
+    if ((int64_t)blockIdx.x >= nblk) return;
   }
   __shared__ double xs[NW][16][kWave + 1];
   __shared__ double gl[NBU * 256];
@@ -155,7 +166,7 @@ __global__ __launch_bounds__(kGramThreads, 1) void trsm_gram_kernel(const double
   for (int i = 0; i < NBU; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
 
   const int64_t ntiles = (m + kWave - 1) / kWave;
-  for (int64_t t = (int64_t)blockIdx.x * NW + wave; t < ntiles; t += (int64_t)gridDim.x * NW) {
+  for (int64_t t = (int64_t)blockIdx.x * NW + wave; t < ntiles; t += nblk * NW) {
     const int64_t row = t * kWave + lane;
     double x[NP];
     load_row<NP, FULL>(x, V, row, m, n, ldv);
@@ -226,10 +237,38 @@ __global__ __launch_bounds__(kGramThreads, 1) void trsm_gram_kernel(const double
 // round all its waves solve with R0, meet at a barrier, then solve with R1.  The two packed
 // factors (16.6 KB each at 64 columns) do not fit the scalar data cache together, so keeping
 // the waves of a CU on the same factor at the same time keeps the coefficient stream hitting.
-template <int NP, bool APPLY_R1, bool FULL, int NW>
+// Batch member (BATCH): factor pointers move by the workspace stride; the input rows are the
+// member's V, or (src_q) its Q holding a stored Q0; the output is the member's Q.
+template <bool BATCH, class PI, class PO>
+__device__ __forceinline__ void member_rows(const MemberStride& ms, int src_q, PI& in, int64_t& m, int64_t& ldin, PO& out, int64_t& ldout) {
+  if constexpr (BATCH) {
+    const int64_t mb = blockIdx.y;
+    if (ms.info != nullptr) {
+      const MemberInfo& mi = member_info(ms, mb);
+      m = mi.m;
+      out = mi.Q;
+      ldout = mi.ldq;
+      in = src_q ? mi.Q : mi.V;
+      ldin = src_q ? mi.ldq : mi.ldv;
+    } else {
+      out += mb * ms.q;
+      in += mb * (src_q ? ms.q : ms.v);
+    }
+  }
+}
+
+template <int NP, bool APPLY_R1, bool FULL, int NW, bool BATCH = false>
 __global__ __launch_bounds__(NW * kWave) void final_kernel(const double* __restrict__ V, int64_t m, int n, int64_t ldv,
                                                           const double* __restrict__ R0pk, const double* __restrict__ R1pk,
-                                                          const int32_t* __restrict__ info, double* __restrict__ Q, int64_t ldq) {
+                                                          const int32_t* __restrict__ info, double* __restrict__ Q, int64_t ldq,
+                                                          MemberStride ms, int src_q) {
+  if constexpr (BATCH) {
+    const int64_t off = (int64_t)blockIdx.y * ms.ws;
+    R0pk += off / (int64_t)sizeof(double);
+    R1pk += off / (int64_t)sizeof(double);
+    info += off / (int64_t)sizeof(int32_t);
+    member_rows<BATCH>(ms, src_q, V, m, ldv, Q, ldq);
+  }
   if (info[0] != 0) return;
   const int wave = threadIdx.x / kWave, lane = lane_id();
   const int64_t ntiles = (m + kWave - 1) / kWave;
@@ -292,11 +331,17 @@ __global__ __launch_bounds__(NW * kWave) void final_mfma_kernel(const double* __
   constexpr int NBU = NB * (NB + 1) / 2;
   if constexpr (BATCH) {
     const int64_t mb = blockIdx.y, off = mb * ms.ws;  // batch member (typed offsets, as above)
-    V += mb * ms.v;
+    member_v(ms, mb, V, m, ldv);
     R0pk += off / (int64_t)sizeof(double);
     R1pk += off / (int64_t)sizeof(double);
     info += off / (int64_t)sizeof(int32_t);
-    Q += mb * ms.q;
+    if (ms.info != nullptr) {
+      const MemberInfo& mi = member_info(ms, mb);
+      Q = mi.Q;
+      ldq = mi.ldq;
+    } else {
+      Q += mb * ms.q;
+    }
   }
   __shared__ double rib[NBU * 256];
   __shared__ double st[NW][16][NP + 1];
@@ -355,13 +400,19 @@ __global__ __launch_bounds__(NW * kWave) void final_mfma_kernel(const double* __
 // cores: R01 sits in LDS, x_lo is read back from the output rows as MFMA operands (16 rows x 4
 // columns per K-step), and each 16-row block of x_lo R01 goes through LDS to the lanes that own
 // those rows.  Only R11 streams through the scalar data cache.
-template <bool FULL, int NW>
+template <bool FULL, int NW, bool BATCH = false>
 __global__ __launch_bounds__(NW * kWave) void solve_hi_kernel(const double* in, int64_t m, int n, int64_t ldin,
                                                              const double* __restrict__ Rbk, const int32_t* __restrict__ info,
-                                                             double* out, int64_t ldout) {
+                                                             double* out, int64_t ldout, MemberStride ms, int src_q) {
   constexpr int H = 64, PK = H * (H + 1) / 2;
   __shared__ double r01[H][H + 1];
   __shared__ double ust[NW][16][H + 1];
+  if constexpr (BATCH) {
+    const int64_t off = (int64_t)blockIdx.y * ms.ws;
+    Rbk += off / (int64_t)sizeof(double);
+    info += off / (int64_t)sizeof(int32_t);
+    member_rows<BATCH>(ms, src_q, in, m, ldin, out, ldout);
+  }
   if (info[0] != 0) return;
   for (int i = threadIdx.x; i < H * H; i += NW * kWave) r01[i / H][i % H] = Rbk[PK + i];
   __syncthreads();
@@ -491,7 +542,8 @@ hipError_t launch_trsm_gram(int np, const double* V, int64_t m, int n, int64_t l
                             double* gpart, double* q0, int64_t ldq, hipStream_t s, const MemberStride& ms) {
   if (ms.count < 1) return hipErrorInvalidValue;
   const dim3 grid(gram_blocks(m), ms.count), block(kGramThreads);
-  const bool full = full_rows(np, n, V, ldv, q0, ldq) && ms.v % 2 == 0 && ms.q % 2 == 0;
+  const bool full = ms.info != nullptr ? (n == np && ms.aligned) : (full_rows(np, n, V, ldv, q0, ldq) && ms.v % 2 == 0 && ms.q % 2 == 0);
+  const bool batch = ms.count > 1 || ms.info != nullptr;
 #define RCQR_GRAM_B(NPV, B)                                                                                                       \
   if (full && q0)                                                                                                                 \
     hipLaunchKernelGGL((trsm_gram_kernel<NPV, true, true, B>), grid, block, 0, s, V, m, n, ldv, r0pk, info, gpart, q0, ldq, ms);   \
@@ -502,7 +554,7 @@ hipError_t launch_trsm_gram(int np, const double* V, int64_t m, int n, int64_t l
   else                                                                                                                            \
     hipLaunchKernelGGL((trsm_gram_kernel<NPV, false, false, B>), grid, block, 0, s, V, m, n, ldv, r0pk, info, gpart, q0, ldq, ms);
 #define RCQR_GRAM(NPV)       \
-  if (ms.count > 1) {        \
+  if (batch) {               \
     RCQR_GRAM_B(NPV, true)   \
   } else {                   \
     RCQR_GRAM_B(NPV, false)  \
@@ -535,10 +587,12 @@ hipError_t prepare_stream_launches() {
 
 hipError_t launch_final(int np, bool apply_r1, const double* V, int64_t m, int n, int64_t ldv, const double* r0pk,
                         const double* r1pk, const int32_t* info, double* Q, int64_t ldq, hipStream_t s, int grid_mult,
-                        const MemberStride& ms) {
+                        const MemberStride& ms, int src_q) {
   if (m <= 0) return hipSuccess;
-  if (ms.count < 1 || (!apply_r1 && ms.count != 1)) return hipErrorInvalidValue;  // batches: the two-factor pass only
-  const bool full = full_rows(np, n, V, ldv, Q, ldq) && ms.v % 2 == 0 && ms.q % 2 == 0;
+  if (ms.count < 1) return hipErrorInvalidValue;
+  const bool full = ms.info != nullptr ? (n == np && ms.aligned)
+                                       : (full_rows(np, n, V, ldv, Q, ldq) && ms.v % 2 == 0 && ms.q % 2 == 0);
+  const bool batch = ms.count > 1 || ms.info != nullptr;
   const int64_t tiles = (m + kWave - 1) / kWave;
   if (apply_r1) {
     // eight waves per workgroup, about two workgroups per CU over the whole pass
@@ -552,7 +606,7 @@ hipError_t launch_final(int np, bool apply_r1, const double* V, int64_t m, int n
   else                                                                                                                          \
     hipLaunchKernelGGL((final_mfma_kernel<NPV, false, NW, B>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq, ms);
 #define RCQR_FINAL_MFMA(NPV)       \
-  if (ms.count > 1) {              \
+  if (batch) {                     \
     RCQR_FINAL_MFMA_B(NPV, true)   \
   } else {                         \
     RCQR_FINAL_MFMA_B(NPV, false)  \
@@ -568,15 +622,21 @@ hipError_t launch_final(int np, bool apply_r1, const double* V, int64_t m, int n
     return hipGetLastError();
   }
   // one factor: Q0 = V R0^{-1} only (persistent, one workgroup per CU)
+#define RCQR_FINAL_B(NPV, NWV, B)                                                                                                \
+  if (full)                                                                                                                     \
+    hipLaunchKernelGGL((final_kernel<NPV, false, true, NWV, B>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq, ms, src_q); \
+  else                                                                                                                          \
+    hipLaunchKernelGGL((final_kernel<NPV, false, false, NWV, B>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq, ms, src_q);
 #define RCQR_FINAL(NPV, NWV)                                                                                                    \
   {                                                                                                                             \
     int64_t g = (tiles + NWV - 1) / NWV;                                                                                        \
     if (g > final_grid()) g = final_grid();                                                                                     \
-    const dim3 grid((unsigned)g), block(NWV * kWave);                                                                           \
-    if (full)                                                                                                                   \
-      hipLaunchKernelGGL((final_kernel<NPV, false, true, NWV>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq);    \
-    else                                                                                                                        \
-      hipLaunchKernelGGL((final_kernel<NPV, false, false, NWV>), grid, block, 0, s, V, m, n, ldv, r0pk, r1pk, info, Q, ldq);   \
+    const dim3 grid((unsigned)g, ms.count), block(NWV * kWave);                                                                 \
+    if (batch) {                                                                                                                \
+      RCQR_FINAL_B(NPV, NWV, true)                                                                                              \
+    } else {                                                                                                                    \
+      RCQR_FINAL_B(NPV, NWV, false)                                                                                             \
+    }                                                                                                                           \
   }
   switch (np) {
     case 16: RCQR_FINAL(16, 16) break;
@@ -585,6 +645,7 @@ hipError_t launch_final(int np, bool apply_r1, const double* V, int64_t m, int n
     default: return hipErrorInvalidValue;
   }
 #undef RCQR_FINAL
+#undef RCQR_FINAL_B
   return hipGetLastError();
 }
 
@@ -613,22 +674,28 @@ hipError_t launch_apply_rinv(int np, double* Q, int64_t m, int n, int64_t ldq, c
 }
 
 hipError_t launch_solve128(const double* in, int64_t m, int n, int64_t ldin, const double* rbk, const int32_t* info, double* out,
-                           int64_t ldout, hipStream_t s, int grid_mult) {
+                           int64_t ldout, hipStream_t s, int grid_mult, const MemberStride& ms, int src_q) {
   if (m <= 0) return hipSuccess;
-  if (n <= 64 || n > 128) return hipErrorInvalidValue;
-  // x_lo = v_lo R00^{-1} into the output's first 64 columns (R00 packed leads the blocked format)
-  const hipError_t e = launch_final(64, false, in, m, 64, ldin, rbk, rbk, info, out, ldout, s);
+  if (n <= 64 || n > 128 || ms.count < 1) return hipErrorInvalidValue;
+  // x_lo = v_lo R00^{-1} into the output's first 64 columns (R00 packed leads the blocked format);
+  // the 64-column view of 16-byte aligned rows with even leading dimensions is aligned too
+  const hipError_t e = launch_final(64, false, in, m, 64, ldin, rbk, rbk, info, out, ldout, s, 2, ms, src_q);
   if (e != hipSuccess) return e;
   constexpr int NW = 8;
   const int64_t tiles = (m + kWave - 1) / kWave;
   int64_t g = (tiles + NW - 1) / NW;
   if (g > (int64_t)grid_mult * final_grid()) g = (int64_t)grid_mult * final_grid();
-  const dim3 grid((unsigned)g), block(NW * kWave);
-  const bool full = n == 128 && full_rows(64, 64, in, ldin, out, ldout);
-  if (full)
-    hipLaunchKernelGGL((solve_hi_kernel<true, NW>), grid, block, 0, s, in, m, n, ldin, rbk, info, out, ldout);
-  else
-    hipLaunchKernelGGL((solve_hi_kernel<false, NW>), grid, block, 0, s, in, m, n, ldin, rbk, info, out, ldout);
+  const dim3 grid((unsigned)g, ms.count), block(NW * kWave);
+  const bool batch = ms.count > 1 || ms.info != nullptr;
+  const bool full = n == 128 && (ms.info != nullptr ? ms.aligned : (full_rows(64, 64, in, ldin, out, ldout) && ms.v % 2 == 0 && ms.q % 2 == 0));
+#define RCQR_HI(F, B) \
+  hipLaunchKernelGGL((solve_hi_kernel<F, NW, B>), grid, block, 0, s, in, m, n, ldin, rbk, info, out, ldout, ms, src_q);
+  if (batch) {
+    if (full) { RCQR_HI(true, true) } else { RCQR_HI(false, true) }
+  } else {
+    if (full) { RCQR_HI(true, false) } else { RCQR_HI(false, false) }
+  }
+#undef RCQR_HI
   return hipGetLastError();
 }
 

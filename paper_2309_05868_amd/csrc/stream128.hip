@@ -24,11 +24,25 @@ __device__ __forceinline__ void syrk_operands(double (&F)[8], const double* __re
   }
 }
 
-template <bool FULL>
+template <bool FULL, bool BATCH>
 __global__ __launch_bounds__(2 * kSyrkPairs * kWave) void syrk128_kernel(const double* __restrict__ Q0, int64_t m, int n, int64_t ldq,
-                                                                       const int32_t* __restrict__ info, double* __restrict__ gpart) {
+                                                                       const int32_t* __restrict__ info, double* __restrict__ gpart,
+                                                                       MemberStride ms) {
   constexpr int NB = 8, NBU = NB * (NB + 1) / 2, HALF = NBU / 2;  // 36 blocks, 18 per wave
   __shared__ double gl[NBU * 256];
+  if constexpr (BATCH) {  // batch member: its stored Q0 (in its Q) and workspace slice
+    const int64_t mb = blockIdx.y, off = mb * ms.ws;
+    info += off / (int64_t)sizeof(int32_t);
+    gpart += off / (int64_t)sizeof(double);
+    if (ms.info != nullptr) {
+      const MemberInfo& mi = member_info(ms, mb);
+      Q0 = mi.Q;
+      ldq = mi.ldq;
+      m = mi.m;
+    } else {
+      Q0 += mb * ms.q;
+    }
+  }
   if (info[0] != 0) return;
   const int wave = threadIdx.x / kWave, lane = lane_id();
   const int set = wave & 1, pair = wave >> 1;
@@ -76,12 +90,22 @@ __global__ __launch_bounds__(2 * kSyrkPairs * kWave) void syrk128_kernel(const d
   for (int i = threadIdx.x; i < NBU * 256; i += 2 * kSyrkPairs * kWave) outp[i] = gl[i];
 }
 
-hipError_t launch_syrk128(const double* Q0, int64_t m, int n, int64_t ldq, const int32_t* info, double* gpart, hipStream_t s) {
-  const dim3 grid(kGramBlocks), block(2 * kSyrkPairs * kWave);
-  if (n == 128)
-    hipLaunchKernelGGL(syrk128_kernel<true>, grid, block, 0, s, Q0, m, n, ldq, info, gpart);
-  else
-    hipLaunchKernelGGL(syrk128_kernel<false>, grid, block, 0, s, Q0, m, n, ldq, info, gpart);
+hipError_t launch_syrk128(const double* Q0, int64_t m, int n, int64_t ldq, const int32_t* info, double* gpart, hipStream_t s,
+                          const MemberStride& ms) {
+  if (ms.count < 1) return hipErrorInvalidValue;
+  const dim3 grid(kGramBlocks, ms.count), block(2 * kSyrkPairs * kWave);
+  const bool batch = ms.count > 1 || ms.info != nullptr;
+  if (batch) {
+    if (n == 128)
+      hipLaunchKernelGGL((syrk128_kernel<true, true>), grid, block, 0, s, Q0, m, n, ldq, info, gpart, ms);
+    else
+      hipLaunchKernelGGL((syrk128_kernel<false, true>), grid, block, 0, s, Q0, m, n, ldq, info, gpart, ms);
+  } else {
+    if (n == 128)
+      hipLaunchKernelGGL((syrk128_kernel<true, false>), grid, block, 0, s, Q0, m, n, ldq, info, gpart, ms);
+    else
+      hipLaunchKernelGGL((syrk128_kernel<false, false>), grid, block, 0, s, Q0, m, n, ldq, info, gpart, ms);
+  }
   return hipGetLastError();
 }
 

@@ -9,10 +9,11 @@ other compute units to the streaming passes of the others.  Completions are foun
 events; a request's latency is its device completion time minus its arrival time.
 
 With max_batch > 1 the loop also batches: when the head request is admitted, requests behind it
-that have already arrived and have the same shape (backend.shape_key) join it, in arrival order,
-up to max_batch and within the memory budget, and run as one rcqr_factor_batch launch on the
-slot (each with its own seed; results bitwise those of separate calls).  Same-shaped requests can
-thereby start ahead of earlier requests of other shapes; the head itself never waits.
+that have already arrived and have the same column shape (backend.shape_key: n, s1, s2; any row
+count) join it, in arrival order, up to max_batch and within the memory budget, and run as one
+rcqr_factor_ragged launch on the slot (each with its own V, Q, R and seed; results bitwise those
+of separate calls).  Requests of that shape can thereby start ahead of earlier requests of other
+shapes; the head itself never waits.
 
 The scheduling logic is independent of the GPU (`Scheduler` with a backend); `GpuBackend` runs
 the factorizations through the C ABI, `serve()` wires the two together.
@@ -103,11 +104,14 @@ class Scheduler:
                                     "slot": None}
                     progressed = True
                     continue
-                if used + fp > self.budget:
+                idle = self.backend.idle_bytes() if hasattr(self.backend, "idle_bytes") else 0
+                if used + fp + idle > self.budget and idle > 0:
+                    idle -= self.backend.evict_idle(used + fp + idle - self.budget)
+                if used + fp + idle > self.budget:
                     break  # wait for memory; keep arrival order
                 pending.popleft()
                 slot = free_slots.pop()
-                group = self._followers(collections.deque([idx]) + pending, req, now, self.budget - used - fp)
+                group = self._followers(collections.deque([idx]) + pending, req, now, self.budget - used - fp - idle)
                 if group:
                     for g in group:
                         pending.remove(g)
@@ -130,26 +134,35 @@ class Scheduler:
 class GpuBackend:
     """Runs requests through the C ABI on one HIP stream per slot; V comes from get_V(req).
 
-    Plans are cached per (slot, shape) for the shapes rcqr_factor_batch takes (shape_key), at
-    most plans_per_slot per slot, least recently used evicted: a request of such a shape reuses
-    its slot's workspace (a lone request runs as a batch of one, bitwise the result of a single
-    rcqr_factor with its seed).  Other shapes get a plan of their own per request.  A slot runs
-    one launch at a time and is handed back only after its launch has completed, so its cached
-    plans, its pinned seed buffer and its device seed buffer are free again whenever the
-    scheduler launches on it.  Cached workspaces stay allocated until close(); the memory
-    budget of the scheduler counts the requests in flight."""
+    Requests of one column shape (n, s1, s2; plain FP64) share rcqr_factor_ragged launches
+    whatever their row counts: each member reads its own V and writes its own Q and R (no copy of
+    V), and is bitwise the result of a single rcqr_factor with its seed.  Plans are cached per
+    (slot, column shape), at most plans_per_slot per slot, least recently used evicted; a cached
+    plan holds batch_hint workspace slices sized for m_cap rows (or more when a request needs
+    it) and is remade larger when a batch needs more.  With plan flags (single-precision sketch,
+    second Cholesky QR) every request gets a plan of its own.  A slot runs one launch at a time
+    and is handed back only after its launch has completed, so its cached plans and seed buffers
+    are free whenever the scheduler launches on it.
 
-    def __init__(self, get_V, slots, device="cuda:0", flags=0, keep_outputs=False, batch_hint=1, plans_per_slot=4):
+    Memory: footprint(req) counts what a request holds while in flight (its Q and R and its
+    workspace slice at the cached plans' row count); idle_bytes() counts the workspace slices
+    cached plans keep beyond the launches in flight, and evict_idle(nbytes) frees least recently
+    used idle plans; the scheduler admits a request only while in-flight footprints plus idle
+    plans fit the budget, evicting idle plans when that makes the room."""
+
+    def __init__(self, get_V, slots, device="cuda:0", flags=0, keep_outputs=False, batch_hint=1, plans_per_slot=4, m_cap=0,
+                 batching=True):
         self.device = torch.device(device)
+        self.batching = bool(batching)
         self.batch_plans = {}
-        self.batch_hint = int(batch_hint)
+        self.batch_hint = max(1, int(batch_hint))
         self.plans_per_slot = max(1, int(plans_per_slot))
+        self.m_cap = int(m_cap)
         self.get_V = get_V
         self.flags = flags
         self.keep = keep_outputs
         self.streams = [torch.cuda.Stream(self.device) for _ in range(slots)]
-        self.seed_host = [None] * slots
-        self.seed_dev = [None] * slots
+        self.busy = set()  # slots with a launch in flight
         self.outputs = {}
         self.reset_clock()
 
@@ -164,15 +177,67 @@ class GpuBackend:
     def now(self):
         return time.perf_counter() - self.t0_host
 
+    def _plan_rows(self, req):
+        return max(self.m_cap, req["m"])
+
     def footprint(self, req):
         m, n = req["m"], req["n"]
-        return workspace_bytes(m, n, req["s1"], req["s2"], self.flags) + 8 * m * n + 8 * n * n
+        mw = self._plan_rows(req) if self.shape_key(req) is not None else m
+        return workspace_bytes(mw, n, req["s1"], req["s2"], self.flags) + 8 * m * n + 8 * n * n
+
+    def idle_bytes(self):
+        """Workspace bytes of cached plans beyond what the launches in flight use."""
+        return sum(p.workspace.numel() for (slot, _), p in self.batch_plans.items() if slot not in self.busy)
+
+    def evict_idle(self, nbytes):
+        """Free least recently used cached plans of idle slots until nbytes are freed (or none left)."""
+        freed = 0
+        for key in list(self.batch_plans):
+            if freed >= nbytes:
+                break
+            if key[0] in self.busy:
+                continue
+            p = self.batch_plans.pop(key)
+            freed += p.workspace.numel()
+            p.close()
+        return freed
+
+    def close(self):
+        for p in self.batch_plans.values():
+            p.close()
+        self.batch_plans = {}
+
+    def shape_key(self, req):
+        """Requests with equal keys can share one rcqr_factor_ragged launch (plain FP64, any m);
+        None (a plan and an rcqr_factor call per request) with flags or with batching off."""
+        if self.flags != 0 or not self.batching:
+            return None
+        return (req["n"], req["s1"], req["s2"])
+
+    def _batch_plan(self, slot, key, count, m_need):
+        """The slot's cached plan for `key`, made (or remade larger) when it cannot hold `count`
+        members of up to m_need rows."""
+        cached = self.batch_plans.pop((slot, key), None)
+        if cached is None or cached.batch < count or cached.m < m_need:
+            m_plan = max(m_need, self.m_cap, cached.m if cached is not None else 0)
+            count = max(count, cached.batch if cached is not None else 0)
+            if cached is not None:
+                cached.close()
+            mine = [k for k in self.batch_plans if k[0] == slot]
+            while len(mine) >= self.plans_per_slot:  # dict order = least recently used first
+                self.batch_plans.pop(mine.pop(0)).close()
+            n, s1, s2 = key
+            cached = Plan(m_plan, n, s1, s2, 0, device=self.device, stream=self.streams[slot], batch=max(count, self.batch_hint))
+        self.batch_plans[(slot, key)] = cached  # (re)inserted last: most recently used
+        return cached
 
     def launch(self, req, slot):
         if self.shape_key(req) is not None:
             return self.launch_batch([req], slot)
         stream = self.streams[slot]
         V = self.get_V(req)
+        stream.wait_stream(torch.cuda.current_stream(self.device))  # V is ready on the caller's stream
+        self.busy.add(slot)
         with torch.cuda.stream(stream):
             plan = Plan(req["m"], req["n"], req["s1"], req["s2"], req["seed"], device=self.device, stream=stream,
                         flags=self.flags)
@@ -181,65 +246,26 @@ class GpuBackend:
             plan.factor(V, Q, R, check=False)
             done = torch.cuda.Event(enable_timing=True)
             done.record(stream)
-        return {"req": req, "plan": plan, "Q": Q, "R": R, "event": done}
-
-    def close(self):
-        for p in self.batch_plans.values():
-            p.close()
-        self.batch_plans = {}
-
-    def shape_key(self, req):
-        """Requests with equal keys can share one rcqr_factor_batch launch (n <= 64, s2 <= 256, FP64)."""
-        if self.flags != 0 or req["n"] > 64 or req["s2"] > 256:
-            return None
-        return (req["m"], req["n"], req["s1"], req["s2"])
-
-    def _batch_plan(self, slot, key, count):
-        """The slot's cached plan for `key`, made (or remade larger) when it cannot hold `count`."""
-        cached = self.batch_plans.pop((slot, key), None)
-        if cached is None or cached.batch < count:
-            if cached is not None:
-                cached.close()
-            mine = [k for k in self.batch_plans if k[0] == slot]
-            while len(mine) >= self.plans_per_slot:  # dict order = least recently used first
-                self.batch_plans.pop(mine.pop(0)).close()
-            m, n, s1, s2 = key
-            cached = Plan(m, n, s1, s2, 0, device=self.device, stream=self.streams[slot], batch=max(count, self.batch_hint))
-        self.batch_plans[(slot, key)] = cached  # (re)inserted last: most recently used
-        return cached
-
-    def _seeds(self, slot, seeds):
-        """Per-request seeds on the device, staged through the slot's pinned buffer."""
-        k = len(seeds)
-        if self.seed_host[slot] is None or self.seed_host[slot].numel() < k:
-            cap = max(k, self.batch_hint)
-            self.seed_host[slot] = torch.empty(cap, dtype=torch.int64, pin_memory=True)
-            self.seed_dev[slot] = torch.empty(cap, dtype=torch.int64, device=self.device)
-        d = self.seed_dev[slot][:k]
-        if k == 1:  # a lone request: the seed goes in as a fill kernel's argument, no copy
-            d.fill_(int(seeds[0]))
-            return d
-        self.seed_host[slot].numpy()[:k] = seeds
-        d.copy_(self.seed_host[slot][:k], non_blocking=True)
-        return d
+        return {"req": req, "plan": plan, "Q": Q, "R": R, "V": V, "event": done, "slot": slot}
 
     def launch_batch(self, reqs, slot):
         stream = self.streams[slot]
         key = self.shape_key(reqs[0])
-        k = len(reqs)
+        Vs = [self.get_V(r) for r in reqs]
+        stream.wait_stream(torch.cuda.current_stream(self.device))  # the V are ready on the caller's stream
+        self.busy.add(slot)
         with torch.cuda.stream(stream):
-            Vb = self.get_V(reqs[0]).unsqueeze(0) if k == 1 else torch.stack([self.get_V(r) for r in reqs])
-            seeds = self._seeds(slot, [r["seed"] for r in reqs])
-            plan = self._batch_plan(slot, key, k)
-            Q, R = plan.factor_batch(Vb, seeds=seeds)
+            plan = self._batch_plan(slot, key, len(reqs), max(r["m"] for r in reqs))
+            Qs, Rs = plan.factor_ragged(Vs, seeds=[r["seed"] for r in reqs])
             done = torch.cuda.Event(enable_timing=True)
             done.record(stream)
-        return {"reqs": reqs, "plan": plan, "Q": Q, "R": R, "event": done, "keep": Vb}
+        return {"reqs": reqs, "plan": plan, "Q": Qs, "R": Rs, "V": Vs, "event": done, "slot": slot}
 
     def poll(self, handle):
         if not handle["event"].query():
             return None
         end = self.t0_event.elapsed_time(handle["event"]) * 1e-3
+        self.busy.discard(handle["slot"])
         if "reqs" in handle:  # a batch (its plan stays cached for the slot)
             sts = [st for st, _ in handle["plan"].info_batch(len(handle["reqs"]))]
             if self.keep:
@@ -272,14 +298,15 @@ def latency_summary(run):
 
 
 def serve(requests, get_V, slots=4, budget_bytes=32 << 30, device="cuda:0", flags=0, keep_outputs=False, max_batch=1,
-          backend=None):
+          backend=None, m_cap=0, batching=True):
     """Run the request list with continuous batching; returns (run, summary, backend).
 
     With `backend` (a GpuBackend with at least `slots` streams) the run reuses it and its cached
     plans, restarting its clock; the caller closes it.  Otherwise a new one is made and closed."""
     own = backend is None
     if own:
-        backend = GpuBackend(get_V, slots, device=device, flags=flags, keep_outputs=keep_outputs, batch_hint=max_batch)
+        backend = GpuBackend(get_V, slots, device=device, flags=flags, keep_outputs=keep_outputs, batch_hint=max_batch, m_cap=m_cap,
+                             batching=batching)
     else:
         if slots > len(backend.streams):
             raise ValueError(f"{slots} slots need as many streams; the backend has {len(backend.streams)}")

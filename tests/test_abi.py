@@ -41,9 +41,9 @@ def test_workspace_bytes_and_shape_checks(lib):
     assert rc.workspace_bytes(10_000, 100, 20_000, 400) > 0
     assert rc.workspace_bytes(10_000, 129, 40_000, 600) == 0  # n beyond the kernels
     assert rc.workspace_bytes(2**31, 8, 128, 32) == 0   # row index must fit 31 bits
-    for flags in (rc.FLAG_SKETCH_FP32, rc.FLAG_SKETCH_FP32 | rc.FLAG_GEMM_BF16, rc.FLAG_REORTH, 7):
+    for flags in (rc.FLAG_SKETCH_FP32, rc.FLAG_SKETCH_FP32 | rc.FLAG_GEMM_BF16, rc.FLAG_REORTH, 7, rc.FLAG_SKETCH_AT_PLAN, 15):
         assert rc.workspace_bytes(10_000, 16, 512, 64, flags) == ws
-    assert rc.workspace_bytes(10_000, 16, 512, 64, 8) == 0
+    assert rc.workspace_bytes(10_000, 16, 512, 64, 16) == 0   # unknown flag bit
     assert rc.workspace_bytes(10_000, 16, 512, 64, rc.FLAG_GEMM_BF16) == 0
 
 
@@ -62,7 +62,7 @@ def test_plan_rejects_bad_arguments_on_host(lib):
     assert lib.rcqr_plan(ctypes.byref(h), 1000, 16, 512, 64, 0, 0, None, 0, None) == rc.E_INVALID
     assert lib.rcqr_plan(ctypes.byref(h), 1000, 16, 8, 64, 0, 0, ctypes.c_void_p(256), 1 << 30, None) == rc.E_INVALID
     assert lib.rcqr_plan(ctypes.byref(h), 1000, 129, 40_000, 600, 0, 0, ctypes.c_void_p(256), 1 << 30, None) == rc.E_UNSUPPORTED
-    assert lib.rcqr_plan(ctypes.byref(h), 1000, 16, 512, 64, 0, 8, ctypes.c_void_p(256), 1 << 30, None) == rc.E_INVALID
+    assert lib.rcqr_plan(ctypes.byref(h), 1000, 16, 512, 64, 0, 16, ctypes.c_void_p(256), 1 << 30, None) == rc.E_INVALID
     assert lib.rcqr_plan(ctypes.byref(h), 1000, 16, 512, 64, 0, rc.FLAG_GEMM_BF16, ctypes.c_void_p(256), 1 << 30,
                          None) == rc.E_INVALID  # BF16 product needs the FP32 sketch
     assert lib.rcqr_plan(ctypes.byref(h), 1000, 16, 512, 64, 0, 0, ctypes.c_void_p(8), 1 << 30, None) == rc.E_INVALID
@@ -140,11 +140,42 @@ def test_plan_rejects_bad_arguments_on_host(lib):
         assert lib.rcqr_info_member(h, -1, ctypes.byref(st), ctypes.byref(col)) == rc.E_INVALID
     finally:
         assert lib.rcqr_destroy(h) == rc.OK
+    # batches run the plain FP64 method: a plan with flags is refused before anything is launched
     ws2 = rc.workspace_bytes(m, 100, 2000, 200)
-    assert lib.rcqr_plan(ctypes.byref(h), m, 100, 2000, 200, 0, 0, ctypes.c_void_p(1 << 20), ws2, None) == rc.OK
+    assert lib.rcqr_plan(ctypes.byref(h), m, 100, 2000, 200, 0, rc.FLAG_REORTH, ctypes.c_void_p(1 << 20), ws2, None) == rc.OK
     try:
         V, Q, R = ctypes.c_void_p(1 << 30), ctypes.c_void_p(1 << 31), ctypes.c_void_p(1 << 32)
-        assert lib.rcqr_factor_batch(h, 1, V, 100, m * 100, Q, 100, m * 100, R, 100, 100 * 100, None) == rc.E_UNSUPPORTED  # n > 64
+        assert lib.rcqr_factor_batch(h, 1, V, 100, m * 100, Q, 100, m * 100, R, 100, 100 * 100, None) == rc.E_UNSUPPORTED
+        one = (rc._RaggedMember * 1)(rc._RaggedMember(1 << 30, 1 << 31, 1 << 32, m, 100, 100, 100, 7))
+        assert lib.rcqr_factor_ragged(h, 1, one) == rc.E_UNSUPPORTED
+    finally:
+        assert lib.rcqr_destroy(h) == rc.OK
+
+
+def test_ragged_argument_errors_need_no_device():
+    # every rejection happens on the host, before the member table is copied or a kernel launched
+    lib = rc.lib()
+    h = ctypes.c_void_p()
+    m, n = 1000, 16
+    ws1 = rc.workspace_bytes(m, n, 512, 64)
+    assert lib.rcqr_plan(ctypes.byref(h), m, n, 512, 64, 0, 0, ctypes.c_void_p(1 << 20), 2 * ws1, None) == rc.OK
+    try:
+        def member(mm=500, ldv=n, ldq=n, ldr=n, V=1 << 30, Q=1 << 31, R=1 << 32):
+            return rc._RaggedMember(V, Q, R, mm, ldv, ldq, ldr, 3)
+
+        def call(*members):
+            t = (rc._RaggedMember * len(members))(*members)
+            return lib.rcqr_factor_ragged(h, len(members), t)
+
+        assert call(member(), member(), member()) == rc.E_INVALID      # 3 members, workspace for 2
+        assert lib.rcqr_factor_ragged(h, 0, None) == rc.E_INVALID
+        assert lib.rcqr_factor_ragged(None, 1, (rc._RaggedMember * 1)(member())) == rc.E_INVALID
+        assert call(member(mm=m + 1)) == rc.E_INVALID                    # more rows than the plan
+        assert call(member(mm=n - 1)) == rc.E_INVALID                    # fewer rows than columns
+        assert call(member(ldv=n - 1)) == rc.E_INVALID
+        assert call(member(ldr=n - 1)) == rc.E_INVALID
+        assert call(member(V=0)) == rc.E_INVALID                         # null buffers
+        assert call(member(Q=1 << 30, ldq=n + 1)) == rc.E_INVALID       # Q = V with another leading dimension
     finally:
         assert lib.rcqr_destroy(h) == rc.OK
 

@@ -129,10 +129,11 @@ def test_factor_batch_limits():
         V = torch.zeros((3, 1000, 16), dtype=torch.float64, device="cuda")
         with pytest.raises(rc.RcqrError):
             p.factor_batch(V)  # more members than the workspace holds
-    with rc.Plan(1000, 100, 2000, 200, seed=1, batch=2) as p:
+    with rc.Plan(1000, 100, 2000, 200, seed=1, batch=2, flags=rc.FLAG_REORTH) as p:
         V = torch.zeros((2, 1000, 100), dtype=torch.float64, device="cuda")
-        with pytest.raises(rc.RcqrError):
-            p.factor_batch(V)  # more than 64 columns
+        with pytest.raises(rc.RcqrError) as e:
+            p.factor_batch(V)  # plan flags: batches run the plain FP64 method only
+        assert e.value.status == rc.E_UNSUPPORTED
     torch.cuda.synchronize()
 
 

@@ -277,3 +277,20 @@ def test_gram_grid_edges(m):
     assert np.linalg.norm(np.eye(n) - Q.T @ Q) <= tgt
     assert np.linalg.norm(V - Q @ R) / np.linalg.norm(V) <= tgt
     assert rel(R, lapack_r(V)) <= 1e-10
+
+
+@pytest.mark.parametrize("m,n,s1,s2", [(50_000, 64, 8192, 256), (20_001, 128, 32_768, 512), (10_000, 8, 128, 32),
+                                       (30_000, 32, 2048, 128)])
+def test_sketch_at_plan_is_bitwise_the_per_call_sketch(m, n, s1, s2):
+    # S1 made once by rcqr_plan (RCQR_FLAG_SKETCH_AT_PLAN) gives bitwise the factorizations of a
+    # plan that makes it in every call, over several inputs in a row (the index is reused)
+    say("sketch at plan", m, n, s1, s2)
+    Vs = [dev(synth.make_V(m, n, k, seed=80 + i)) for i, k in enumerate((1e3, 1e10, 1e14))]
+    with rc.Plan(m, n, s1, s2, seed=8) as p0, rc.Plan(m, n, s1, s2, seed=8, flags=rc.FLAG_SKETCH_AT_PLAN) as p1:
+        for V in Vs + Vs[:1]:
+            Qa, Ra = p0.factor(V)
+            Qb, Rb = p1.factor(V)
+            torch.cuda.synchronize()
+            assert torch.equal(Qa, Qb) and torch.equal(Ra, Rb)
+            ia, ib = p0.intermediates(), p1.intermediates()
+            assert torch.equal(ia["W1"], ib["W1"])

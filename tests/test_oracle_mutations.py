@@ -69,6 +69,18 @@ def check_rand_cholqr():
     assert rc.orth_error(o["Q"]) <= 10 * 6 * rc.U_PAPER
 
 
+def check_cholqr2_and_scholqr3_r():
+    # the comparators' R against LAPACK's R of V (the thin QR is unique; kappa 1e4 keeps both
+    # inside their range): a product taken in the wrong order is off by O(kappa^2 u) relative
+    V = synth.make_V(2000, 6, 1e4, seed=5)
+    Rl = lapack_r(V)
+    for fn in (rc.cholqr2, rc.shifted_cholqr3):
+        Q, R, st, _ = fn(V)
+        assert st == rc.OK
+        assert np.linalg.norm(R - Rl) <= 1e-11 * np.linalg.norm(Rl)
+        assert rc.orth_error(Q) <= 10 * 6 * rc.U_PAPER
+
+
 def _philox_no_key_bump(counter, key, rounds=philox.ROUNDS):
     c0, c1, c2, c3 = (int(x) for x in counter)
     k0, k1 = (int(x) for x in key)
@@ -132,6 +144,7 @@ MUTATIONS = [
     ("householder tau divides by alpha", dense, "householder_r", _householder_wrong_tau, check_householder),
     ("cholesky drops off-diagonal update", dense, "cholesky_upper", _cholesky_no_offdiag_update, check_cholesky),
     ("substitution reads a transposed operand", dense, "forward_subst_rows", _subst_transposed, check_substitution),
+    ("comparators' R = R_first R_second", rc, "triu_product", _product_wrong_order, check_cholqr2_and_scholqr3_r),
 ]
 
 E2E_MUTATIONS = [

@@ -145,37 +145,69 @@ class _FakePlan:
     made = []
 
     def __init__(self, m, n, s1, s2, seed, device=None, stream=None, batch=1):
-        self.key, self.batch, self.closed = (m, n, s1, s2), batch, False
+        self.m, self.key, self.batch, self.closed = m, (n, s1, s2), batch, False
+        self.workspace = _FakeWorkspace(1000 * m * batch)
         _FakePlan.made.append(self)
 
     def close(self):
         self.closed = True
 
 
+class _FakeWorkspace:
+    def __init__(self, nbytes):
+        self.nbytes = nbytes
+
+    def numel(self):
+        return self.nbytes
+
+
+def _fake_backend(srv, batch_hint=2, plans_per_slot=2, m_cap=0):
+    be = object.__new__(srv.GpuBackend)
+    be.batch_plans, be.batch_hint, be.plans_per_slot, be.m_cap = {}, batch_hint, plans_per_slot, m_cap
+    be.device, be.streams, be.busy, be.flags, be.batching = None, [None, None], set(), 0, True
+    return be
+
+
 def test_gpu_backend_plan_cache_is_lru_per_slot(monkeypatch):
-    # host logic of the per-slot plan cache, with a stand-in Plan (no device needed)
+    # host logic of the per-slot plan cache (keyed by column shape), with a stand-in Plan
     from paper_2309_05868_amd import serve as srv
 
     monkeypatch.setattr(srv, "Plan", _FakePlan)
     _FakePlan.made = []
-    be = object.__new__(srv.GpuBackend)
-    be.batch_plans, be.batch_hint, be.plans_per_slot = {}, 2, 2
-    be.device, be.streams = None, [None, None]
-    A, B, C = (100, 8, 128, 32), (200, 8, 128, 32), (300, 8, 128, 32)
-    pa = be._batch_plan(0, A, 1)
-    assert pa.batch == 2                              # sized for the batch hint
-    assert be._batch_plan(0, A, 2) is pa              # reused while it holds the count
-    pb = be._batch_plan(0, B, 1)
-    pb1 = be._batch_plan(1, B, 1)                     # other slot: its own plan
+    be = _fake_backend(srv)
+    A, B, C = (8, 128, 32), (16, 512, 64), (32, 2048, 128)
+    assert be.shape_key({"n": 8, "s1": 128, "s2": 32, "m": 5}) == A   # any row count
+    pa = be._batch_plan(0, A, 1, 100)
+    assert pa.batch == 2 and pa.m == 100                 # sized for the batch hint and the rows
+    assert be._batch_plan(0, A, 2, 80) is pa             # reused while it holds count and rows
+    pb = be._batch_plan(0, B, 1, 100)
+    pb1 = be._batch_plan(1, B, 1, 100)                   # other slot: its own plan
     assert pb1 is not pb
-    assert be._batch_plan(0, A, 1) is pa              # A used last on slot 0, so B is the oldest
-    pc = be._batch_plan(0, C, 1)                      # third shape on slot 0 evicts B only
+    assert be._batch_plan(0, A, 1, 100) is pa            # A used last on slot 0, so B is the oldest
+    pc = be._batch_plan(0, C, 1, 100)                    # third shape on slot 0 evicts B only
     assert pb.closed and not pa.closed and not pc.closed and not pb1.closed
     assert set(be.batch_plans) == {(0, A), (0, C), (1, B)}
-    pa4 = be._batch_plan(0, A, 4)                     # too small: remade larger, old one closed
+    pa4 = be._batch_plan(0, A, 4, 100)                   # too few members: remade larger
     assert pa.closed and pa4.batch == 4 and not pc.closed
+    pa5 = be._batch_plan(0, A, 1, 300)                   # too few rows: remade with more
+    assert pa4.closed and pa5.m == 300 and pa5.batch == 4
     be.close()
     assert all(p.closed for p in _FakePlan.made) and be.batch_plans == {}
+
+
+def test_gpu_backend_idle_plans_counted_and_evicted(monkeypatch):
+    from paper_2309_05868_amd import serve as srv
+
+    monkeypatch.setattr(srv, "Plan", _FakePlan)
+    be = _fake_backend(srv, batch_hint=1, m_cap=10)
+    A, B = (8, 128, 32), (16, 512, 64)
+    pa = be._batch_plan(0, A, 1, 10)
+    pb = be._batch_plan(1, B, 1, 10)
+    assert be.idle_bytes() == pa.workspace.numel() + pb.workspace.numel()
+    be.busy.add(1)                                        # slot 1 has a launch in flight
+    assert be.idle_bytes() == pa.workspace.numel()
+    assert be.evict_idle(1) == pa.workspace.numel()       # only the idle slot's plan goes
+    assert pa.closed and not pb.closed and be.idle_bytes() == 0
 
 
 def test_serve_rejects_more_slots_than_backend_streams():
