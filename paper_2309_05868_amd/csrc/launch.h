@@ -213,6 +213,11 @@ hipError_t launch_apply_rinv(int np, double* Q, int64_t m, int n, int64_t ldq, c
 // In a batch the input rows are the member's V, or its Q when src_q; the output is its Q.
 hipError_t launch_solve128(const double* in, int64_t m, int n, int64_t ldin, const double* rbk, const int32_t* info, double* out,
                            int64_t ldout, hipStream_t s, int grid_mult = 2, const MemberStride& ms = MemberStride(), int src_q = 0);
+// R1^{-1} of a blocked packed factor as the 36 upper 16 x 16 blocks (rinv: 36 * 256 doubles), and
+// Q = Q0 R1^{-1} in place on the stored Q0 from them (65..128 columns).
+hipError_t launch_rinv128(const double* rbk, const int32_t* info, double* rinv, hipStream_t s, const MemberStride& ms = MemberStride());
+hipError_t launch_apply_rinv128(double* Q, int64_t m, int n, int64_t ldq, const double* rinv, const int32_t* info, int grid_mult,
+                                hipStream_t s, const MemberStride& ms = MemberStride());
 // Gram partials of Q0 (kGramBlocks compact partials of 36 upper 16x16 blocks).
 hipError_t launch_syrk128(const double* Q0, int64_t m, int n, int64_t ldq, const int32_t* info, double* gpart, hipStream_t s,
                           const MemberStride& ms = MemberStride());

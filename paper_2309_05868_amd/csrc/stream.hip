@@ -171,9 +171,13 @@ __global__ __launch_bounds__(kGramThreads, 1) void trsm_gram_kernel(const double
     double x[NP];
     load_row<NP, FULL>(x, V, row, m, n, ldv);
     rowsolve<NP>(x, R0pk);
+    // when Q0 is stored, each lane writes its solved row from registers (the lines of a row are
+    // completed by consecutive stores and merge in L2; no extra registers for a staged copy)
+    if constexpr (STORE) {
+      if (row < m) store_row<NP, FULL>(x, q0, row, n, ldq);
+    }
     // transpose 16-column blocks through LDS into MFMA operands:
-    // F[a][s] (lane l) = X[4s + l/16][16a + l%16]; when Q0 is stored, it is written from the same
-    // staging, eight lanes per 128-byte row segment
+    // F[a][s] (lane l) = X[4s + l/16][16a + l%16]
     double F[NB][16];
 #pragma unroll
     for (int a = 0; a < NB; ++a) {
@@ -182,24 +186,6 @@ __global__ __launch_bounds__(kGramThreads, 1) void trsm_gram_kernel(const double
       wave_lds_sync();
 #pragma unroll
       for (int s = 0; s < 16; ++s) F[a][s] = xs[wave][lane & 15][4 * s + (lane >> 4)];
-      if constexpr (STORE) {
-        const int cp = 2 * (lane & 7);
-        const int col = 16 * a + cp;
-#pragma unroll
-        for (int it = 0; it < 8; ++it) {
-          const int rr = (lane >> 3) + 8 * it;
-          const int64_t r = t * kWave + rr;
-          if (r < m) {
-            double* dst = q0 + r * ldq + col;
-            if constexpr (FULL) {
-              *reinterpret_cast<double2*>(dst) = double2{xs[wave][cp][rr], xs[wave][cp + 1][rr]};
-            } else {
-              if (col < n) dst[0] = xs[wave][cp][rr];
-              if (col + 1 < n) dst[1] = xs[wave][cp + 1][rr];
-            }
-          }
-        }
-      }
       wave_lds_sync();
     }
 #pragma unroll
@@ -504,21 +490,30 @@ __global__ __launch_bounds__(NW * kWave) void apply_rinv_kernel(double* Q, int64
   const int64_t nblk16 = (m + 15) / 16;
   for (int64_t b16 = (int64_t)blockIdx.x * NW + wave; b16 < nblk16; b16 += (int64_t)gridDim.x * NW) {
     const int64_t arow = b16 * 16 + li;
-    double a[NP / 4];
+    // operands one 16-column block (four K-steps) at a time, the next block's loads in flight
+    auto load_blk = [&](int kb, double (&a)[4]) {
 #pragma unroll
-    for (int k = 0; k < NP / 4; ++k) {
-      const int col = 4 * k + lq;
-      a[k] = (arow < m && (FULL || col < n)) ? Q[arow * ldq + col] : 0.0;
-    }
+      for (int kk = 0; kk < 4; ++kk) {
+        const int col = 16 * kb + 4 * kk + lq;
+        a[kk] = (arow < m && (FULL || col < n)) ? Q[arow * ldq + col] : 0.0;
+      }
+    };
+    double a[2][4];
+    load_blk(0, a[0]);
     d4 acc[NB];
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < NP / 4; ++k) {
+    for (int kb = 0; kb < NB; ++kb) {
+      __builtin_amdgcn_sched_barrier(0);  // keep the operand reads of one block together
+      if (kb + 1 < NB) load_blk(kb + 1, a[(kb + 1) & 1]);
 #pragma unroll
-      for (int cb = k / 4; cb < NB; ++cb)
-        acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k], rib[upper_blk(k / 4, cb, NB) * 256 + (4 * (k % 4) + lq) * 16 + li],
-                                                       acc[cb], 0, 0, 0);
+      for (int kk = 0; kk < 4; ++kk) {
+#pragma unroll
+        for (int cb = kb; cb < NB; ++cb)
+          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kb & 1][kk], rib[upper_blk(kb, cb, NB) * 256 + (4 * kk + lq) * 16 + li],
+                                                         acc[cb], 0, 0, 0);
+      }
     }
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb) {
@@ -530,6 +525,152 @@ __global__ __launch_bounds__(NW * kWave) void apply_rinv_kernel(double* Q, int64
       }
     }
   }
+}
+
+// 65..128 columns, Algorithm 2 step 3: R1^{-1} formed once per factorization (R1 = chol(G) has the
+// condition number of Q0, O(1); Section 4's remark on the conditioning of randQR's Q), then
+// Q = Q0 R1^{-1} as one product on the matrix cores over the stored Q0 (apply_rinv128_kernel).
+// Row i of R^{-1} solves x R = e_i by block substitution over the blocked factor
+// [R00 | R01; 0 | R11]: x_lo = e_i R00^{-1} (zero below row 64), x_hi = (e_i,hi - x_lo R01) R11^{-1};
+// lane i of wave 0 takes rows 0..63, lane i of wave 1 rows 64..127.  The upper 16 x 16 blocks
+// of R^{-1} (36 of them, row-major blocks in upper_blk order) go to rinv.
+__global__ __launch_bounds__(2 * kWave) void rinv128_kernel(const double* __restrict__ Rbk, const int32_t* __restrict__ info,
+                                                           double* __restrict__ rinv, MemberStride ms) {
+  constexpr int H = 64, PK = H * (H + 1) / 2, NB = 8;
+  {
+    const int64_t off = (int64_t)blockIdx.y * ms.ws;  // batch member
+    Rbk += off / (int64_t)sizeof(double);
+    info += off / (int64_t)sizeof(int32_t);
+    rinv += off / (int64_t)sizeof(double);
+  }
+  if (info[0] != 0) return;
+  const int wave = threadIdx.x / kWave, lane = lane_id();
+  const int row = wave * H + lane;
+  double lo[H], hi[H];
+#pragma unroll
+  for (int c = 0; c < H; ++c) {
+    lo[c] = (wave == 0 && c == lane) ? 1.0 : 0.0;
+    hi[c] = (wave == 1 && c == lane) ? 1.0 : 0.0;
+  }
+  if (wave == 0) {
+    rowsolve<H>(lo, Rbk);
+    // hi -= lo R01 (R01 dense 64 x 64 row-major after R00's packed triangle); k ascending
+    const double* __restrict__ R01 = Rbk + PK;
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const double xk = lo[k];
+#pragma unroll
+      for (int j = 0; j < H; ++j) hi[j] = __builtin_fma(-xk, R01[k * H + j], hi[j]);
+    }
+  }
+  rowsolve<H>(hi, Rbk + PK + H * H);
+  const int a = row / 16;
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb) {
+    if (cb >= a) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int col = 16 * cb + j;
+        rinv[upper_blk(a, cb, NB) * 256 + (row & 15) * 16 + j] = col < H ? lo[col] : hi[col - H];
+      }
+    }
+  }
+}
+
+// Q = Q0 R1^{-1} in place, 65..128 columns (rows padded to 128): the upper blocks of R1^{-1} in LDS,
+// the MFMA operands read straight from the stored Q0 rows (16 rows x 4 columns per K-step); each
+// 16-row block is read completely before it is overwritten.
+template <bool FULL, int NW, bool BATCH>
+__global__ __launch_bounds__(NW * kWave) void apply_rinv128_kernel(double* Q, int64_t m, int n, int64_t ldq,
+                                                                  const double* __restrict__ rinv, const int32_t* __restrict__ info,
+                                                                  MemberStride ms) {
+  constexpr int NP = 128, NB = 8, NBU = NB * (NB + 1) / 2;
+  __shared__ double rib[NBU * 256];
+  if constexpr (BATCH) {
+    const int64_t mb = blockIdx.y, off = mb * ms.ws;
+    rinv += off / (int64_t)sizeof(double);
+    info += off / (int64_t)sizeof(int32_t);
+    if (ms.info != nullptr) {
+      const MemberInfo& mi = member_info(ms, mb);
+      Q = mi.Q;
+      ldq = mi.ldq;
+      m = mi.m;
+    } else {
+      Q += mb * ms.q;
+    }
+  }
+  if (info[0] != 0) return;
+  for (int i = threadIdx.x; i < NBU * 256; i += NW * kWave) rib[i] = rinv[i];
+  __syncthreads();
+  const int wave = threadIdx.x / kWave, lane = lane_id();
+  const int li = lane & 15, lq = lane >> 4;
+  const int64_t nblk16 = (m + 15) / 16;
+  for (int64_t b16 = (int64_t)blockIdx.x * NW + wave; b16 < nblk16; b16 += (int64_t)gridDim.x * NW) {
+    const int64_t arow = b16 * 16 + li;
+    // operands one 16-column block (four K-steps) at a time, the next block's loads in flight
+    auto load_blk = [&](int kb, double (&a)[4]) {
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int col = 16 * kb + 4 * kk + lq;
+        a[kk] = (arow < m && (FULL || col < n)) ? Q[arow * ldq + col] : 0.0;
+      }
+    };
+    double a[2][4];
+    load_blk(0, a[0]);
+    d4 acc[NB];
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kb = 0; kb < NB; ++kb) {
+      __builtin_amdgcn_sched_barrier(0);  // keep the operand reads of one block together
+      if (kb + 1 < NB) load_blk(kb + 1, a[(kb + 1) & 1]);
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+#pragma unroll
+        for (int cb = kb; cb < NB; ++cb)
+          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kb & 1][kk], rib[upper_blk(kb, cb, NB) * 256 + (4 * kk + lq) * 16 + li],
+                                                         acc[cb], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+      const int col = 16 * cb + li;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t r = b16 * 16 + lq + 4 * e;
+        if (r < m && (FULL || col < n)) Q[r * ldq + col] = acc[cb][e];
+      }
+    }
+  }
+}
+
+static int final_grid();
+
+hipError_t launch_rinv128(const double* rbk, const int32_t* info, double* rinv, hipStream_t s, const MemberStride& ms) {
+  if (ms.count < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(rinv128_kernel, dim3(1, ms.count), dim3(2 * kWave), 0, s, rbk, info, rinv, ms);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_rinv128(double* Q, int64_t m, int n, int64_t ldq, const double* rinv, const int32_t* info, int grid_mult,
+                                hipStream_t s, const MemberStride& ms) {
+  if (m <= 0) return hipSuccess;
+  if (n <= 64 || n > 128 || ms.count < 1) return hipErrorInvalidValue;
+  constexpr int NW = 8;
+  const int64_t blocks = (m + 15) / 16;
+  int64_t g = (blocks + NW - 1) / NW;
+  if (g > (int64_t)grid_mult * final_grid()) g = (int64_t)grid_mult * final_grid();
+  const dim3 grid((unsigned)g, ms.count), block(NW * kWave);
+  const bool batch = ms.count > 1 || ms.info != nullptr;
+  const bool full = n == 128;
+#define RCQR_AR128(F, B) hipLaunchKernelGGL((apply_rinv128_kernel<F, NW, B>), grid, block, 0, s, Q, m, n, ldq, rinv, info, ms);
+  if (batch) {
+    if (full) { RCQR_AR128(true, true) } else { RCQR_AR128(false, true) }
+  } else {
+    if (full) { RCQR_AR128(true, false) } else { RCQR_AR128(false, false) }
+  }
+#undef RCQR_AR128
+  return hipGetLastError();
 }
 
 static bool full_rows(int np, int n, const void* a, int64_t lda, const void* b, int64_t ldb) {

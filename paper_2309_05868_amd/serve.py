@@ -132,7 +132,12 @@ class Scheduler:
 
 
 class GpuBackend:
-    """Runs requests through the C ABI on one HIP stream per slot; V comes from get_V(req).
+    """Runs requests through the C ABI on one HIP stream per slot; V comes from get_V(req), either a
+    tensor whose contents are complete when get_V returns, or (tensor, event) with a HIP event
+    (torch.cuda.Event) recorded after the work that writes it, which the slot's stream waits for.
+    (Waiting on the caller's whole stream instead would record an event on the legacy default
+    stream, which orders it after the work of every slot: measured, it serialised the slots and
+    tripled the p50 latency.)
 
     Requests of one column shape (n, s1, s2; plain FP64) share rcqr_factor_ragged launches
     whatever their row counts: each member reads its own V and writes its own Q and R (no copy of
@@ -231,12 +236,25 @@ class GpuBackend:
         self.batch_plans[(slot, key)] = cached  # (re)inserted last: most recently used
         return cached
 
+    def _inputs(self, reqs, stream):
+        """The requests' V; the slot stream waits for the ones that come with a readiness event."""
+        Vs = []
+        for r in reqs:
+            got = self.get_V(r)
+            if isinstance(got, tuple):
+                V, ready = got
+                if ready is not None:
+                    stream.wait_event(ready)
+            else:
+                V = got
+            Vs.append(V)
+        return Vs
+
     def launch(self, req, slot):
         if self.shape_key(req) is not None:
             return self.launch_batch([req], slot)
         stream = self.streams[slot]
-        V = self.get_V(req)
-        stream.wait_stream(torch.cuda.current_stream(self.device))  # V is ready on the caller's stream
+        V = self._inputs([req], stream)[0]
         self.busy.add(slot)
         with torch.cuda.stream(stream):
             plan = Plan(req["m"], req["n"], req["s1"], req["s2"], req["seed"], device=self.device, stream=stream,
@@ -251,8 +269,7 @@ class GpuBackend:
     def launch_batch(self, reqs, slot):
         stream = self.streams[slot]
         key = self.shape_key(reqs[0])
-        Vs = [self.get_V(r) for r in reqs]
-        stream.wait_stream(torch.cuda.current_stream(self.device))  # the V are ready on the caller's stream
+        Vs = self._inputs(reqs, stream)
         self.busy.add(slot)
         with torch.cuda.stream(stream):
             plan = self._batch_plan(slot, key, len(reqs), max(r["m"] for r in reqs))

@@ -126,3 +126,31 @@ def test_reused_backend_with_plan_evictions_equals_solo_results():
                 Q, R = p.factor(Vs[r["seed"]])
             torch.cuda.synchronize()
             assert torch.equal(Q, Qs) and torch.equal(R, Rs), r
+
+
+def test_request_with_readiness_event_waits_for_its_producer():
+    # V is written on another stream behind a spin; get_V hands over (V, event) and the served
+    # result must be that of the finished V (the slot stream waits for the event)
+    reqs = [{"arrival_s": 0.0, "m": 20_000 + 1000 * i, "n": 16, "s1": 512, "s2": 64, "seed": 700 + i, "kappa": 1e6}
+            for i in range(3)]
+    src = {r["seed"]: torch.from_numpy(synth.make_V(r["m"], r["n"], r["kappa"], r["seed"])).to("cuda") for r in reqs}
+    dst = {k: torch.zeros_like(v) for k, v in src.items()}
+    torch.cuda.synchronize()
+    prod = torch.cuda.Stream()
+    ready = {}
+    with torch.cuda.stream(prod):
+        for k in dst:
+            torch.cuda._sleep(20_000_000)  # a bounded spin: the copy lands well after the launch
+            dst[k].copy_(src[k])
+            ev = torch.cuda.Event()
+            ev.record(prod)
+            ready[k] = ev
+    run, summary, backend = srv.serve(reqs, lambda r: (dst[r["seed"]], ready[r["seed"]]), slots=2, budget_bytes=4 << 30,
+                                      keep_outputs=True, max_batch=4)
+    assert summary["completed"] == 3 and summary["ok"] == 3
+    for r in reqs:
+        Qs, Rs = backend.outputs[r["seed"]]
+        with rc.Plan(r["m"], r["n"], r["s1"], r["s2"], r["seed"]) as p:
+            Q, R = p.factor(src[r["seed"]])
+        torch.cuda.synchronize()
+        assert torch.equal(Q, Qs) and torch.equal(R, Rs), r
