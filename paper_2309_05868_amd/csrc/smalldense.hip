@@ -525,21 +525,32 @@ __global__ __launch_bounds__(CholShape<NP>::NWV * kWave) void cholesky_kernel(co
     __syncthreads();
   }
   const double* rpv = NP <= 64 ? rp : rprev;
-  for (int idx = t; idx < n * n; idx += blockDim.x) {
-    const int r = idx / n, k = idx % n;
-    double acc = 0.0;
-    if (k >= r) {
-      int m = r;
-      for (; m + 8 <= k + 1; m += 8) {  // eight independent loads in flight
-        double pv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) pv[u] = rpv[(m + u) * n + k];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc = __builtin_fma(Rl[r * NP + m + u], pv[u], acc);
+  // R = R1 Rprev (Algorithm 3, step 3) on the matrix cores: each wave takes 16 x 16 output blocks
+  // (a, b); an upper block sums only the K-steps where both triangles are nonzero (rows 16a to
+  // 16b + 15 of Rprev), a lower block is zero.  Operand lanes as in the streaming passes:
+  // A[l % 16][l / 16], B[l / 16][l % 16], result element e of lane l at row l / 16 + 4e, column l % 16.
+  {
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    const int li = l & 15, lq = l >> 4;
+    const int nbn = (n + 15) / 16;
+    for (int blk = w; blk < nbn * nbn; blk += NWV) {
+      const int a = blk / nbn, b = blk % nbn;
+      d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+      if (a <= b) {
+        const int ra = 16 * a + li, cb = 16 * b + li;
+        for (int ks = 4 * a; ks < 4 * b + 4; ++ks) {
+          const int kk = 4 * ks + lq;
+          const double av = (ra < n && kk < n) ? Rl[ra * NP + kk] : 0.0;
+          const double bv = (kk < n && cb < n) ? rpv[kk * n + cb] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
       }
-      for (; m <= k; ++m) acc = __builtin_fma(Rl[r * NP + m], rpv[m * n + k], acc);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = 16 * a + lq + 4 * e, c = 16 * b + li;
+        if (r < n && c < n) r_out[(int64_t)r * ldr + c] = (c >= r) ? acc[e] : 0.0;
+      }
     }
-    r_out[(int64_t)r * ldr + k] = acc;
   }
 }
 
