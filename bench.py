@@ -844,6 +844,11 @@ def main():
     roofline["kernel"] = dom
     roofline["kernel_ms"] = round(phases[dom], 4)
     roofline["algorithmic_bytes"] = bytes_
+    # the same launch against the FP64 roof (vector FMAs and FP64 MFMAs share that pipe): the two
+    # streaming passes sit near the ridge point, so both fractions are reported
+    roofline["algorithmic_flops"] = flops
+    roofline["fp64_tflops"] = round(achieved_tf, 2)
+    roofline["fp64_frac"] = round(achieved_tf / FP64_PEAK_TFLOPS, 4)
     if roofline.get("traffic") is not None:
         roofline["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, copy-calibrated)"
 
