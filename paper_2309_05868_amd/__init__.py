@@ -72,6 +72,18 @@ class _RaggedMember(ctypes.Structure):
                 ("seed", _c_u64)]
 
 
+# rcqr_member_t as one numpy record (the same 64-byte layout as _RaggedMember)
+def _member_dtype():
+    import numpy as np
+
+    return np.dtype([("V", "<u8"), ("Q", "<u8"), ("R", "<u8"), ("m", "<i8"), ("ldv", "<i8"), ("ldq", "<i8"), ("ldr", "<i8"),
+                     ("seed", "<u8")])
+
+
+_MEMBER_DTYPE = _member_dtype()
+assert _MEMBER_DTYPE.itemsize == ctypes.sizeof(_RaggedMember)
+
+
 class RcqrError(RuntimeError):
     def __init__(self, status, what, column=0):
         self.status = int(status)
@@ -253,28 +265,43 @@ class Plan:
     def factor_ragged(self, Vs, Qs=None, Rs=None, seeds=None):
         """rcqr_factor_ragged: Algorithm 3 on matrices of the plan's n, s1, s2 and their own row
         counts (each at most the plan's m), in one set of launches.  Vs: list of CUDA float64
-        row-major tensors; Qs / Rs: outputs (allocated when None; Q may be V); seeds: one int per
-        member (default: the plan's seed + b).  Returns (Qs, Rs); statuses via info_batch."""
+        row-major tensors; Qs / Rs: outputs (allocated when None, as views of one tensor each; Q
+        may be V); seeds: one int per member (default: the plan's seed + b).  Returns (Qs, Rs);
+        statuses via info_batch.  The member table is built as one array (a serving loop calls
+        this once per batch)."""
+        import numpy as np
+
         k = len(Vs)
         if k < 1 or k > self.batch:
             raise ValueError(f"need 1 .. {self.batch} members (the plan's batch)")
+        n = self.n
+        f64 = torch.float64
+        for b, V in enumerate(Vs):  # one cheap test per member; the full check names the problem
+            if not (isinstance(V, torch.Tensor) and V.dtype is f64 and V.is_cuda and V.dim() == 2 and V.shape[1] == n
+                    and V.stride(1) == 1 and V.stride(0) >= n):
+                _check_matrix(V, V.shape[0] if V.dim() == 2 else -1, n, f"V[{b}]")
+        ms = [V.shape[0] for V in Vs]
+        dev = Vs[0].device
         Qs = list(Qs) if Qs is not None else [None] * k
         Rs = list(Rs) if Rs is not None else [None] * k
+        for b in range(k):  # caller-given outputs are checked; fresh ones are views of one tensor
+            if Qs[b] is not None:
+                _check_matrix(Qs[b], ms[b], n, f"Q[{b}]")
+            if Rs[b] is not None:
+                _check_matrix(Rs[b], n, n, f"R[{b}]")
+        miss = [b for b in range(k) if Qs[b] is None]
+        if miss:
+            qall = torch.empty((sum(ms[b] for b in miss), n), dtype=f64, device=dev)
+            for b, Q in zip(miss, torch.split(qall, [ms[b] for b in miss])):
+                Qs[b] = Q
+        miss = [b for b in range(k) if Rs[b] is None]
+        if miss:
+            for b, R in zip(miss, torch.empty((len(miss), n, n), dtype=f64, device=dev).unbind(0)):
+                Rs[b] = R
         seeds = list(seeds) if seeds is not None else [self.seed + b for b in range(k)]
-        table = (_RaggedMember * k)()
-        for b in range(k):
-            V = Vs[b]
-            m = V.shape[0] if V.dim() == 2 else -1
-            _check_matrix(V, m, self.n, f"V[{b}]")
-            if Qs[b] is None:
-                Qs[b] = torch.empty((m, self.n), dtype=torch.float64, device=V.device)
-            if Rs[b] is None:
-                Rs[b] = torch.empty((self.n, self.n), dtype=torch.float64, device=V.device)
-            _check_matrix(Qs[b], m, self.n, f"Q[{b}]")
-            _check_matrix(Rs[b], self.n, self.n, f"R[{b}]")
-            table[b] = _RaggedMember(V.data_ptr(), Qs[b].data_ptr(), Rs[b].data_ptr(), m, V.stride(0), Qs[b].stride(0),
-                                     Rs[b].stride(0), int(seeds[b]) & 0xFFFFFFFFFFFFFFFF)
-        _check(lib().rcqr_factor_ragged(self._h, k, table), "rcqr_factor_ragged")
+        table = np.array([(V.data_ptr(), Q.data_ptr(), R.data_ptr(), m, V.stride(0), Q.stride(0), R.stride(0),
+                           int(sd) & 0xFFFFFFFFFFFFFFFF) for V, Q, R, m, sd in zip(Vs, Qs, Rs, ms, seeds)], dtype=_MEMBER_DTYPE)
+        _check(lib().rcqr_factor_ragged(self._h, k, ctypes.c_void_p(table.ctypes.data)), "rcqr_factor_ragged")
         self._ragged_keep = (Vs, Qs, Rs)  # the buffers stay referenced until the next call
         return Qs, Rs
 

@@ -127,6 +127,26 @@ def test_same_shape_requests_share_a_launch():
     assert res[0]["batch"] == 3 and res[2]["batch"] == 2
 
 
+def test_no_batching_without_a_backlog():
+    # two same-shape arrivals and two slots: each starts on its own slot; with four arrivals and
+    # two slots (three waiting behind the head) the head takes the others along
+    spec = [(0.0, 0.002, 10)] * 2
+    rq = reqs(spec)
+    for r in rq:
+        r["shape"] = "A"
+    be = FakeBatchBackend()
+    run = Scheduler(be, slots=2, budget_bytes=10**6, max_batch=4).run(rq)
+    assert be.batches == []  # both went through single launches
+    assert sorted(slot for _, slot, _ in be.launched) == [0, 1]
+    assert all(r["batch"] == 1 for r in run["results"])
+    rq = reqs([(0.0, 0.002, 10)] * 4)
+    for r in rq:
+        r["shape"] = "A"
+    be = FakeBatchBackend()
+    Scheduler(be, slots=2, budget_bytes=10**6, max_batch=4).run(rq)
+    assert be.batches[0] == [0, 1, 2, 3]
+
+
 def test_batches_respect_budget_and_unbatchable_requests():
     spec = [(0.0, 0.002, 40)] * 4
     rq = reqs(spec)
