@@ -24,6 +24,7 @@ the factorizations through the C ABI, `serve()` wires the two together.
 """
 
 import collections
+import itertools
 import time
 
 import torch
@@ -55,21 +56,29 @@ class Scheduler:
         if key is None:
             return []
         out = []
-        for idx in list(pending)[1:]:
+        joinable = getattr(self.backend, "joinable", None)
+        for idx in itertools.islice(pending, 1, None):
             if len(out) + 1 >= self.max_batch:
                 break
             req = self.requests[idx]
             if req["arrival_s"] > now:
                 break
-            if self.backend.shape_key(req) == key and (not hasattr(self.backend, "joinable") or self.backend.joinable(head, req)):
-                fp = self.backend.footprint(req)
+            if self.backend.shape_key(req) == key and (joinable is None or joinable(head, req)):
+                fp = self._footprint(idx)
                 if fp <= room:
                     out.append(idx)
                     room -= fp
         return out
 
+    def _footprint(self, idx):
+        fp = self._fps.get(idx)
+        if fp is None:
+            fp = self._fps[idx] = self.backend.footprint(self.requests[idx])
+        return fp
+
     def run(self, requests, idle_sleep_s=0.0):
         self.requests = requests
+        self._fps = {}
         order = sorted(range(len(requests)), key=lambda i: requests[i]["arrival_s"])
         pending = collections.deque(order)
         free_slots = list(range(self.slots))[::-1]
@@ -100,7 +109,7 @@ class Scheduler:
                 req = requests[idx]
                 if req["arrival_s"] > now:
                     break
-                fp = self.backend.footprint(req)
+                fp = self._footprint(idx)
                 if fp > self.budget:
                     pending.popleft()
                     results[idx] = {"index": idx, "arrival_s": req["arrival_s"], "start_s": None, "end_s": None,
@@ -130,7 +139,7 @@ class Scheduler:
                     for g in group:
                         pending.remove(g)
                     members = [idx] + group
-                    fp += sum(self.backend.footprint(requests[g]) for g in group)
+                    fp += sum(self._footprint(g) for g in group)
                     handle = self.backend.launch_batch([requests[i] for i in members], slot)
                 else:
                     members = [idx]
