@@ -168,11 +168,15 @@ hipError_t launch_gaussian_block(int64_t j0, int64_t nj, int64_t k0, int64_t nk,
 // --- smalldense.hip ------------------------------------------------------------------------
 // R (n x n, row-major, ld n) = R factor of the p x n block `in` (ld ldin, p <= 256) by
 // Householder reflections; rows of R beyond min(p, n) are zero.  One workgroup per block:
-// block b reads rows [b*rows_per_block, ...) and writes out + b*n*n.
+// block b reads rows [b*rows_per_block, ...) and writes out + b*n*n.  With r0 set (the last level
+// of the tree: one block) it writes instead what launch_finalize_r0 would make of that R: r0, its
+// packed padded form r0pk (np columns) and the rank status in info.
 hipError_t launch_qr_blocks(const double* in, int64_t ldin, int64_t p_total, int64_t rows_per_block, int n, double* out,
-                            int nblocks, hipStream_t s, const MemberStride& ms = MemberStride());
+                            int nblocks, hipStream_t s, const MemberStride& ms = MemberStride(), double* r0 = nullptr,
+                            double* r0pk = nullptr, int32_t* info = nullptr, int np = 0);
 hipError_t launch_qr_blocks(const float* in, int64_t ldin, int64_t p_total, int64_t rows_per_block, int n, float* out,
-                            int nblocks, hipStream_t s);
+                            int nblocks, hipStream_t s, const MemberStride& ms = MemberStride(), double* r0 = nullptr,
+                            double* r0pk = nullptr, int32_t* info = nullptr, int np = 0);
 // Sign-normalise the Householder R (rows scaled so the diagonal is positive), check its
 // diagonal (status RANK on zero / non-finite), write R0 (n x n) and its packed padded form.
 // The float overload promotes an FP32 Householder R to FP64 first.

@@ -232,14 +232,17 @@ static rcqr_status_t run_householder(rcqr_plan_t p) {
   int which = 0;
   for (;;) {
     const int64_t nblocks = (rows + rpb - 1) / rpb;
+    if (nblocks == 1) {  // the last level writes R0, its packed form and the rank status itself
+      RCQR_TRY(launch_qr_blocks(in, n, rows, rpb, n, bufs[which], 1, s, MemberStride(), p->at<double>(p->L.r0),
+                                p->at<double>(p->L.r0pk), p->at<int32_t>(p->L.info), sh.np));
+      break;
+    }
     RCQR_TRY(launch_qr_blocks(in, n, rows, rpb, n, bufs[which], (int)nblocks, s));
     in = bufs[which];
     which ^= 1;
-    if (nblocks == 1) break;
     rows = nblocks * n;
     rpb = (kQrRows / n) * n;
   }
-  RCQR_TRY(launch_finalize_r0(in, n, sh.np, p->at<int32_t>(p->L.info), p->at<double>(p->L.r0), p->at<double>(p->L.r0pk), s));
   return RCQR_OK;
 }
 
@@ -543,14 +546,17 @@ static rcqr_status_t run_batch(rcqr_plan_t p, const MemberStride& ms, const doub
     int which = 0;
     for (;;) {
       const int64_t nblocks = (rows + rpb - 1) / rpb;
+      if (nblocks == 1) {  // the last level writes R0, its packed form and the rank status itself
+        RCQR_TRY(launch_qr_blocks(in, n, rows, rpb, n, bufs[which], 1, s, ms, p->at<double>(L.r0), p->at<double>(L.r0pk), info,
+                                  sh.np));
+        break;
+      }
       RCQR_TRY(launch_qr_blocks(in, n, rows, rpb, n, bufs[which], (int)nblocks, s, ms));
       in = bufs[which];
       which ^= 1;
-      if (nblocks == 1) break;
       rows = nblocks * n;
       rpb = (kQrRows / n) * n;
     }
-    RCQR_TRY(launch_finalize_r0(in, n, sh.np, info, p->at<double>(L.r0), p->at<double>(L.r0pk), s, ms));
   }
   // Algorithm 1, step 3 + Algorithm 2, step 1: G = Q0^T Q0 (Q0 stored in Q above 64 columns)
   const int64_t len = gram_compact_len(sh.np);

@@ -17,6 +17,31 @@
 
 namespace rcqr {
 
+// Offset of row k in the packed np x np upper-triangular format.
+__device__ __forceinline__ int packed_row(int k, int np) { return k * np - k * (k - 1) / 2; }
+
+// Position of entry (r, c), c >= r, of an np x np factor in the layout the streaming passes
+// read: packed rows for np <= 64; for np = 128 the blocked layout
+// [R00 packed (64) | R01 dense 64 x 64 row-major | R11 packed (64)].
+__device__ __forceinline__ int factor_index(int np, int r, int c) {
+  if (np <= 64) return packed_row(r, np) + (c - r);
+  constexpr int H = 64, PK = H * (H + 1) / 2;
+  if (r < H && c < H) return packed_row(r, H) + (c - r);
+  if (r < H) return PK + r * H + (c - H);
+  return PK + H * H + packed_row(r - H, H) + (c - r);
+}
+
+// Write entry (r, c), c >= r, of the identity-padded factor: v is R[r][c] for r, c < n; the
+// diagonal is stored as its reciprocal.
+__device__ __forceinline__ void put_packed(double* pk, int np, int n, int r, int c, double v) {
+  double out;
+  if (r < n && c < n)
+    out = (r == c) ? 1.0 / v : v;
+  else
+    out = (r == c) ? 1.0 : 0.0;
+  pk[factor_index(np, r, c)] = out;
+}
+
 // ------------------------------------------------------------------------------------------
 // Householder QR of a p x n block (p <= 256, n <= 128), R factor only, matrix in registers.
 // Sixteen waves; lane l owns rows l, l + 64, l + 128, l + 192, so every column reduction is one
@@ -33,14 +58,36 @@ namespace rcqr {
 constexpr int kQrMaxRows = 256;
 constexpr int kQrWaves = 16;
 
+//
+// Last level of the tree (fin.r0 set, one block): instead of R the kernel writes what R0 is used
+// as, from its registers: R0 with a positive diagonal (rows of R with a negative diagonal entry
+// negated) into fin.r0, its packed padded form into fin.r0pk, and the rank check into info (a
+// zero or non-finite diagonal entry: RCQR_E_RANK and the first such column, unless an earlier
+// step already failed, in which case nothing is written) -- the work of finalize_r0_kernel
+// without a launch of its own.
+struct QrFinal {
+  double* r0;
+  double* r0pk;
+  int32_t* info;
+  int np;
+};
+
 template <int NC, class T>
 __global__ __launch_bounds__(kQrWaves * kWave) void qr_block_kernel(const T* __restrict__ in, int64_t ldin, int64_t p_total,
                                                                     int64_t rows_per_block, int n, T* __restrict__ out,
-                                                                    int64_t member_bytes) {
+                                                                    int64_t member_bytes, QrFinal fin) {
   static_assert(NC % 2 == 0, "columns are owned in pairs");
   constexpr int ER = kQrMaxRows / kWave;  // rows per lane
   in = member_ptr(in, (int64_t)blockIdx.y * member_bytes);  // batch member
   out = member_ptr(out, (int64_t)blockIdx.y * member_bytes);
+  const bool final_level = fin.r0 != nullptr;
+  int32_t status0 = 0;
+  if (final_level) {
+    fin.r0 = member_ptr(fin.r0, (int64_t)blockIdx.y * member_bytes);
+    fin.r0pk = member_ptr(fin.r0pk, (int64_t)blockIdx.y * member_bytes);
+    fin.info = member_ptr(fin.info, (int64_t)blockIdx.y * member_bytes);
+    status0 = fin.info[0];  // read early; used at the end
+  }
   __shared__ T vbuf[2][2][kQrMaxRows];  // [pair parity][first / second reflector of the pair]
   __shared__ T taub[2][2];
   const int wave = threadIdx.x / kWave, lane = lane_id();
@@ -170,66 +217,89 @@ __global__ __launch_bounds__(kQrWaves * kWave) void qr_block_kernel(const T* __r
       for (int q = 0; q < NC; ++q) update(q);
     }
   }
-  T* R = out + (int64_t)blockIdx.x * n * n;
+  if (!final_level) {
+    T* R = out + (int64_t)blockIdx.x * n * n;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const int c = col_of(q);
+#pragma unroll
+      for (int e = 0; e < ER; ++e) {
+        const int r = lane + kWave * e;
+        if (r < n && c < n) R[r * n + c] = (c >= r) ? a[q][e] : T(0);
+      }
+    }
+    return;
+  }
+  if (status0 != 0) return;  // an earlier step failed: keep its status (uniform)
+  __shared__ double dg[kQrMaxRows];
+  __shared__ int bad;  // first failing column (1-based), or a value > n
+  if (threadIdx.x == 0) bad = n + 1;
+  // the diagonal entry of column c sits in its owner's lane c % 64, row slot c / 64
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    const int c = col_of(q);
+    if (c < n && lane == c % kWave) {
+      double d = 0.0;
+#pragma unroll
+      for (int e = 0; e < ER; ++e) d = (e == c / kWave) ? (double)a[q][e] : d;
+      dg[c] = d;
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const double d = dg[j];
+    if (!(d != 0.0) || !isfinite(d)) atomicMin(&bad, j + 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && bad <= n) {
+    fin.info[0] = RCQR_E_RANK;
+    fin.info[1] = bad;
+  }
+  const int np = fin.np;
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
     const int c = col_of(q);
 #pragma unroll
     for (int e = 0; e < ER; ++e) {
       const int r = lane + kWave * e;
-      if (r < n && c < n) R[r * n + c] = (c >= r) ? a[q][e] : T(0);
+      if (r < np && c < np) {
+        double v = 0.0;
+        if (r < n && c < n) {
+          const double x = (double)a[q][e];
+          v = c >= r ? (dg[r] < 0.0 ? -x : x) : 0.0;
+          fin.r0[r * n + c] = v;
+        }
+        if (c >= r) put_packed(fin.r0pk, np, n, r, c, v);
+      }
     }
   }
 }
 
 template <class T>
 static hipError_t qr_blocks_any(const T* in, int64_t ldin, int64_t p_total, int64_t rows_per_block, int n, T* out, int nblocks,
-                                hipStream_t s, const MemberStride& ms) {
+                                hipStream_t s, const MemberStride& ms, QrFinal fin) {
   if (rows_per_block > kQrMaxRows || n > RCQR_MAX_N || n < 1 || ms.count < 1) return hipErrorInvalidValue;
+  if (fin.r0 != nullptr && (nblocks != 1 || fin.np < n || fin.np > 16 * (n <= 32 ? 2 : (n <= 64 ? 4 : 8))))
+    return hipErrorInvalidValue;  // the last level is one block, and its column slots cover np
   const dim3 grid((unsigned)nblocks, ms.count), block(kQrWaves * kWave);
   const int64_t mbytes = ms.ws;
   if (n <= 32)
-    hipLaunchKernelGGL((qr_block_kernel<2, T>), grid, block, 0, s, in, ldin, p_total, rows_per_block, n, out, mbytes);
+    hipLaunchKernelGGL((qr_block_kernel<2, T>), grid, block, 0, s, in, ldin, p_total, rows_per_block, n, out, mbytes, fin);
   else if (n <= 64)
-    hipLaunchKernelGGL((qr_block_kernel<4, T>), grid, block, 0, s, in, ldin, p_total, rows_per_block, n, out, mbytes);
+    hipLaunchKernelGGL((qr_block_kernel<4, T>), grid, block, 0, s, in, ldin, p_total, rows_per_block, n, out, mbytes, fin);
   else
-    hipLaunchKernelGGL((qr_block_kernel<8, T>), grid, block, 0, s, in, ldin, p_total, rows_per_block, n, out, mbytes);
+    hipLaunchKernelGGL((qr_block_kernel<8, T>), grid, block, 0, s, in, ldin, p_total, rows_per_block, n, out, mbytes, fin);
   return hipGetLastError();
 }
 
 hipError_t launch_qr_blocks(const double* in, int64_t ldin, int64_t p_total, int64_t rows_per_block, int n, double* out,
-                            int nblocks, hipStream_t s, const MemberStride& ms) {
-  return qr_blocks_any(in, ldin, p_total, rows_per_block, n, out, nblocks, s, ms);
+                            int nblocks, hipStream_t s, const MemberStride& ms, double* r0, double* r0pk, int32_t* info, int np) {
+  return qr_blocks_any(in, ldin, p_total, rows_per_block, n, out, nblocks, s, ms, QrFinal{r0, r0pk, info, np});
 }
 
 hipError_t launch_qr_blocks(const float* in, int64_t ldin, int64_t p_total, int64_t rows_per_block, int n, float* out,
-                            int nblocks, hipStream_t s) {
-  return qr_blocks_any(in, ldin, p_total, rows_per_block, n, out, nblocks, s, MemberStride());
-}
-
-// Offset of row k in the packed np x np upper-triangular format.
-__device__ __forceinline__ int packed_row(int k, int np) { return k * np - k * (k - 1) / 2; }
-
-// Position of entry (r, c), c >= r, of an np x np factor in the layout the streaming passes
-// read: packed rows for np <= 64; for np = 128 the blocked layout
-// [R00 packed (64) | R01 dense 64 x 64 row-major | R11 packed (64)].
-__device__ __forceinline__ int factor_index(int np, int r, int c) {
-  if (np <= 64) return packed_row(r, np) + (c - r);
-  constexpr int H = 64, PK = H * (H + 1) / 2;
-  if (r < H && c < H) return packed_row(r, H) + (c - r);
-  if (r < H) return PK + r * H + (c - H);
-  return PK + H * H + packed_row(r - H, H) + (c - r);
-}
-
-// Write entry (r, c), c >= r, of the identity-padded factor: v is R[r][c] for r, c < n; the
-// diagonal is stored as its reciprocal.
-__device__ __forceinline__ void put_packed(double* pk, int np, int n, int r, int c, double v) {
-  double out;
-  if (r < n && c < n)
-    out = (r == c) ? 1.0 / v : v;
-  else
-    out = (r == c) ? 1.0 : 0.0;
-  pk[factor_index(np, r, c)] = out;
+                            int nblocks, hipStream_t s, const MemberStride& ms, double* r0, double* r0pk, int32_t* info, int np) {
+  return qr_blocks_any(in, ldin, p_total, rows_per_block, n, out, nblocks, s, ms, QrFinal{r0, r0pk, info, np});
 }
 
 // ------------------------------------------------------------------------------------------
