@@ -177,11 +177,9 @@ hipError_t launch_qr_blocks(const double* in, int64_t ldin, int64_t p_total, int
 hipError_t launch_qr_blocks(const float* in, int64_t ldin, int64_t p_total, int64_t rows_per_block, int n, float* out,
                             int nblocks, hipStream_t s, const MemberStride& ms = MemberStride(), double* r0 = nullptr,
                             double* r0pk = nullptr, int32_t* info = nullptr, int np = 0);
-// Sign-normalise the Householder R (rows scaled so the diagonal is positive), check its
+// Sign-normalise an upper-triangular R (rows scaled so the diagonal is positive), check its
 // diagonal (status RANK on zero / non-finite), write R0 (n x n) and its packed padded form.
-// The float overload promotes an FP32 Householder R to FP64 first.
 hipError_t launch_finalize_r0(const double* rin, int n, int np, int32_t* info, double* r0, double* r0pk, hipStream_t s, const MemberStride& ms = MemberStride());
-hipError_t launch_finalize_r0(const float* rin, int n, int np, int32_t* info, double* r0, double* r0pk, hipStream_t s);
 // Cholesky of the Gram matrix held as compact upper 16x16 blocks; writes G (n x n, upper,
 // lower zero), R1 and its packed padded form, and R = R1 * Rprev into the caller's R
 // (ld ldr).  A non-positive pivot sets status CHOL.

@@ -3,10 +3,12 @@
 //  qr_block_kernel   Householder QR, R factor only (Algorithm 1, step 2; Section 5.1 notes
 //                    only R is needed).  Applied to blocks of <= 256 rows of W; when s2 > 256
 //                    the blocks' R factors are stacked and factored again (a TSQR tree), which
-//                    is still a product of Householder reflections applied to W.
-//  finalize_r0       positive diagonal (rows of R scaled by the sign of their diagonal, which
-//                    makes R0 the unique R of W), rank check, and the packed padded copy the
-//                    streaming passes read (upper triangle row by row, reciprocal diagonal).
+//                    is still a product of Householder reflections applied to W.  The last
+//                    level also makes R0 of its R: positive diagonal (rows scaled by the sign of
+//                    their diagonal, which makes R0 the unique R of W), rank check, and the packed
+//                    padded copy the streaming passes read (upper triangle row by row, reciprocal
+//                    diagonal).
+//  finalize_r0       the same for an R held in memory (the second Cholesky QR's R1 R0).
 //  cholesky_kernel   R1 = chol(G) (Algorithm 2, step 2) and R = R1 R0 (Algorithm 3, step 3);
 //                    with a nonzero shift coefficient c, chol(G + c trace(G) I), the first step
 //                    of shifted CholeskyQR3 (trace(G) = ||V||_F^2 when G = V^T V).
@@ -345,11 +347,6 @@ hipError_t launch_finalize_r0(const double* rin, int n, int np, int32_t* info, d
                               const MemberStride& ms) {
   if (ms.count < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(finalize_r0_kernel<double>, dim3(1, ms.count), dim3(256), 0, s, rin, n, np, info, r0, r0pk, ms.ws);
-  return hipGetLastError();
-}
-
-hipError_t launch_finalize_r0(const float* rin, int n, int np, int32_t* info, double* r0, double* r0pk, hipStream_t s) {
-  hipLaunchKernelGGL(finalize_r0_kernel<float>, dim3(1), dim3(256), 0, s, rin, n, np, info, r0, r0pk, (int64_t)0);
   return hipGetLastError();
 }
 
