@@ -10,9 +10,10 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // G partial = Q0^T Q0 over this workgroup's rows: the 36 upper 16x16 blocks of the 128 x 128
 // matrix on FP64 MFMA.  Four wave pairs per workgroup; waves 2p and 2p+1 read the same 4-row
 // K-steps and accumulate blocks 0..17 and 18..35 respectively (144 accumulator registers
-// each).  The next K-step's operands are loaded before the current step's MFMAs.  Fixed grid,
-// fixed order.
+// each).  The operands of the next kSyrkAhead K-steps are in flight while a step's MFMAs run.
+// Fixed grid, fixed order.
 constexpr int kSyrkPairs = 4;
+constexpr int kSyrkAhead = 3;  // K-steps whose operands are loaded ahead of use
 
 template <bool FULL>
 __device__ __forceinline__ void syrk_operands(double (&F)[8], const double* __restrict__ Q0, int64_t row, int64_t m, int n,
@@ -53,21 +54,27 @@ __global__ __launch_bounds__(2 * kSyrkPairs * kWave) void syrk128_kernel(const d
   const int rsub = lane >> 4, csub = lane & 15;
   const int64_t stride = (int64_t)gridDim.x * kSyrkPairs;
   int64_t st = (int64_t)blockIdx.x * kSyrkPairs + pair;
-  double Fn[NB];
-  syrk_operands<FULL>(Fn, Q0, 4 * st + rsub, m, n, ldq, csub);
-  for (; st < nsteps; st += stride) {
-    double F[NB];
+  // operands of the next kSyrkAhead K-steps in flight (a ring, unrolled so every index is fixed);
+  // steps at or past nsteps read rows past m, which load as zeros and add exact zeros
+  double Fq[kSyrkAhead][NB];
 #pragma unroll
-    for (int a = 0; a < NB; ++a) F[a] = Fn[a];
-    syrk_operands<FULL>(Fn, Q0, 4 * (st + stride) + rsub, m, n, ldq, csub);
-    int ab = 0;
+  for (int k = 0; k < kSyrkAhead; ++k) syrk_operands<FULL>(Fq[k], Q0, 4 * (st + k * stride) + rsub, m, n, ldq, csub);
+  for (; st < nsteps; st += kSyrkAhead * stride) {
 #pragma unroll
-    for (int a = 0; a < NB; ++a) {
+    for (int k = 0; k < kSyrkAhead; ++k) {
+      double F[NB];
 #pragma unroll
-      for (int b = a; b < NB; ++b) {
-        if (set == 0 && ab < HALF) acc[ab] = __builtin_amdgcn_mfma_f64_16x16x4f64(F[a], F[b], acc[ab], 0, 0, 0);
-        if (set == 1 && ab >= HALF) acc[ab - HALF] = __builtin_amdgcn_mfma_f64_16x16x4f64(F[a], F[b], acc[ab - HALF], 0, 0, 0);
-        ++ab;
+      for (int a = 0; a < NB; ++a) F[a] = Fq[k][a];
+      syrk_operands<FULL>(Fq[k], Q0, 4 * (st + (k + kSyrkAhead) * stride) + rsub, m, n, ldq, csub);
+      int ab = 0;
+#pragma unroll
+      for (int a = 0; a < NB; ++a) {
+#pragma unroll
+        for (int b = a; b < NB; ++b) {
+          if (set == 0 && ab < HALF) acc[ab] = __builtin_amdgcn_mfma_f64_16x16x4f64(F[a], F[b], acc[ab], 0, 0, 0);
+          if (set == 1 && ab >= HALF) acc[ab - HALF] = __builtin_amdgcn_mfma_f64_16x16x4f64(F[a], F[b], acc[ab - HALF], 0, 0, 0);
+          ++ab;
+        }
       }
     }
   }
