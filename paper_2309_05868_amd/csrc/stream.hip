@@ -605,31 +605,42 @@ __global__ __launch_bounds__(NW * kWave) void apply_rinv128_kernel(double* Q, in
   const int wave = threadIdx.x / kWave, lane = lane_id();
   const int li = lane & 15, lq = lane >> 4;
   const int64_t nblk16 = (m + 15) / 16;
-  for (int64_t b16 = (int64_t)blockIdx.x * NW + wave; b16 < nblk16; b16 += (int64_t)gridDim.x * NW) {
-    const int64_t arow = b16 * 16 + li;
-    // operands one 16-column block (four K-steps) at a time, the next block's loads in flight
-    auto load_blk = [&](int kb, double (&a)[4]) {
+  const int64_t tstride = (int64_t)gridDim.x * NW;
+  // operands one 16-column block (four K-steps) at a time, four blocks ahead in a ring (into the
+  // wave's next 16-row block near the end of one); a block's rows are all read before its
+  // results are stored, and the next block's rows are other rows
+  auto load_blk = [&](int64_t t, int kb, double (&a)[4]) {
+    const int64_t arow = t * 16 + li;
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int col = 16 * kb + 4 * kk + lq;
-        a[kk] = (arow < m && (FULL || col < n)) ? Q[arow * ldq + col] : 0.0;
-      }
-    };
-    double a[2][4];
-    load_blk(0, a[0]);
+    for (int kk = 0; kk < 4; ++kk) {
+      const int col = 16 * kb + 4 * kk + lq;
+      a[kk] = (t < nblk16 && arow < m && (FULL || col < n)) ? Q[arow * ldq + col] : 0.0;
+    }
+  };
+  int64_t b16 = (int64_t)blockIdx.x * NW + wave;
+  double ring[4][4];
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) load_blk(b16, kb, ring[kb]);
+  for (; b16 < nblk16; b16 += tstride) {
     d4 acc[NB];
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int kb = 0; kb < NB; ++kb) {
+      double a[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) a[kk] = ring[kb % 4][kk];
       __builtin_amdgcn_sched_barrier(0);  // keep the operand reads of one block together
-      if (kb + 1 < NB) load_blk(kb + 1, a[(kb + 1) & 1]);
+      if (kb + 4 < NB)
+        load_blk(b16, kb + 4, ring[kb % 4]);
+      else
+        load_blk(b16 + tstride, kb + 4 - NB, ring[kb % 4]);
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
 #pragma unroll
         for (int cb = kb; cb < NB; ++cb)
-          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kb & 1][kk], rib[upper_blk(kb, cb, NB) * 256 + (4 * kk + lq) * 16 + li],
-                                                         acc[cb], 0, 0, 0);
+          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], rib[upper_blk(kb, cb, NB) * 256 + (4 * kk + lq) * 16 + li], acc[cb], 0,
+                                                         0, 0);
       }
     }
 #pragma unroll
