@@ -428,21 +428,32 @@ __global__ __launch_bounds__(NW * kWave) void solve_hi_kernel(const double* in, 
 #pragma unroll
       for (int c = 0; c < H; ++c) x[c] = 0.0;
     }
-#pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
+    // x_lo operands in halves of eight K-steps, two halves in flight: while one half of a 16-row
+    // block is multiplied, the same half of the next 16-row block is loaded
+    auto load_half = [&](int rb, int h, double (&a)[8]) {
       const int64_t arow = t * kWave + 16 * rb + li;
       const double* xl = out + arow * ldout;
-      double a[16];
 #pragma unroll
-      for (int ks = 0; ks < 16; ++ks) a[ks] = arow < m ? xl[4 * ks + lq] : 0.0;
+      for (int k = 0; k < 8; ++k) a[k] = arow < m ? xl[4 * (8 * h + k) + lq] : 0.0;
+    };
+    double ring[2][8];
+    load_half(0, 0, ring[0]);
+    load_half(0, 1, ring[1]);
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
       d4 acc[4];
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int ks = 0; ks < 16; ++ks) {
+      for (int h = 0; h < 2; ++h) {
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
-          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], r01[4 * ks + lq][16 * cb + li], acc[cb], 0, 0, 0);
+        for (int k = 0; k < 8; ++k) {
+          const int ks = 8 * h + k;
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb)
+            acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ring[h][k], r01[4 * ks + lq][16 * cb + li], acc[cb], 0, 0, 0);
+        }
+        if (rb + 1 < 4) load_half(rb + 1, h, ring[h]);
       }
       // element e of lane l: row 16 rb + l/16 + 4e, column 16 cb + l%16 of x_lo R01
 #pragma unroll
