@@ -61,7 +61,8 @@ hipError_t launch_fill_f64(double* p, int64_t count, double value, hipStream_t s
 // chunks (a multiple of 4 rows each, one workgroup per chunk); one Philox block serves rows
 // 4q .. 4q+3.  hist[chunk][b] = number of rows of the chunk in bucket b.
 // ------------------------------------------------------------------------------------------
-constexpr int kHistLds = 16384;  // buckets counted in LDS; above this, in the chunk's global row
+constexpr int kHistLds = 32768;     // buckets counted in LDS by the hash (128 KiB); above this, in the chunk's global row
+constexpr int kScatterLds = 16384;  // buckets whose counters and segment starts the scatter keeps in LDS
 
 __global__ __launch_bounds__(256) void hash_hist_kernel(int64_t m, uint64_t s1, uint64_t seed, int64_t chunk_rows, uint32_t* __restrict__ codes,
                                                         uint32_t* __restrict__ hist, MemberStride ms) {
@@ -284,7 +285,7 @@ __device__ __forceinline__ void sort_segment(uint32_t* p, int len) {
     if (i < len) p[i] = v[i];
 }
 
-bool bucket_scatter_sorts(int64_t s1) { return s1 <= (int64_t)kHistLds; }
+bool bucket_scatter_sorts(int64_t s1) { return s1 <= (int64_t)kScatterLds; }
 
 // entries[offsets[b] + base(chunk, b) + k] = (row << 1) | signbit for the k-th row of the chunk
 // in bucket b.  k comes from an LDS counter, so the order inside a chunk's segment is whatever
@@ -296,7 +297,7 @@ bool bucket_scatter_sorts(int64_t s1) { return s1 <= (int64_t)kHistLds; }
 __global__ __launch_bounds__(256) void bucket_scatter_kernel(int64_t m, int64_t s1, int64_t chunk_rows, const uint32_t* __restrict__ codes,
                                                              const uint32_t* __restrict__ offsets, uint32_t* __restrict__ hist,
                                                              uint32_t* entries, uint8_t* __restrict__ unsorted, MemberStride ms) {
-  __shared__ uint32_t cur[kHistLds];
+  __shared__ uint32_t cur[kScatterLds];
   {
     const int64_t off = (int64_t)blockIdx.y * ms.ws;  // batch member
     codes = member_ptr(codes, off);
@@ -311,8 +312,8 @@ __global__ __launch_bounds__(256) void bucket_scatter_kernel(int64_t m, int64_t 
       chunk_rows = mi.chunk_rows;
     }
   }
-  __shared__ uint32_t seg0[kHistLds];  // start of this chunk's segment of each bucket
-  const bool in_lds = s1 <= (int64_t)kHistLds;
+  __shared__ uint32_t seg0[kScatterLds];  // start of this chunk's segment of each bucket
+  const bool in_lds = s1 <= (int64_t)kScatterLds;
   uint32_t* gh = hist + (int64_t)blockIdx.x * s1;
   if (in_lds) {
     for (int64_t b = threadIdx.x; b < s1; b += blockDim.x) {

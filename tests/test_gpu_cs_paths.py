@@ -4,8 +4,9 @@ Section 4.2: applying S1 adds or subtracts subsets of the rows of V).
   * LDS copies, every wave of a workgroup looping over several 256-row chunks: the workgroup
     count is capped (256 to 1024 partials), so past about 1024 x 256 rows each workgroup owns
     thousands of rows and all four per-wave copies accumulate before their fixed-order sum;
-  * bucket index with the bucket counters in global memory (s1 > 16384), which every
-    128-column configuration with s1 = 2 n^2 = 32768 runs;
+  * bucket index with the scatter's counters in global memory (s1 > 16384; the gather then sorts
+    every bucket), which every 128-column configuration with s1 = 2 n^2 = 32768 runs: the hash
+    histogram still in LDS up to s1 = 32768, in global memory above;
   * both in FP64 and with the single-precision sketch.
 
 Integer-valued V makes every bucket sum exact in FP64 (and in FP32 while the partial sums stay
@@ -60,8 +61,10 @@ def device_w1(V, n, s1, s2, seed, flags=0):
 #   1,000,003 x 32, s1 64: 512 partials of 2048 rows;
 #   700,000 x 64, s1 64:   256 partials of 2816 rows.
 LDS_CASES = [(2_100_001, 8, 128), (600_000, 16, 256), (1_000_003, 32, 64), (700_000, 64, 64)]
-# bucket index with global bucket counters (s1 > 16384), n = 128, 100 and 64 (s1 just above the limit)
-GLOBAL_CASES = [(100_000, 128, 32_768), (60_000, 100, 20_000), (200_001, 64, 16_385)]
+# bucket index with global scatter counters (s1 > 16384): n = 128, 100 and 64 (s1 just above that limit),
+# and with the hash histogram in global memory too (s1 > 32768): n = 128 and 64
+GLOBAL_CASES = [(100_000, 128, 32_768), (60_000, 100, 20_000), (200_001, 64, 16_385), (150_000, 128, 32_769),
+                (120_000, 64, 40_000)]
 
 
 @pytest.mark.parametrize("m,n,s1", LDS_CASES + GLOBAL_CASES)
@@ -74,7 +77,7 @@ def test_w1_integer_bit_exact_fp64(m, n, s1):
     np.testing.assert_array_equal(W1, apply_countsketch(V, b, g, s1))
 
 
-@pytest.mark.parametrize("m,n,s1", [(2_100_001, 8, 128), (600_000, 16, 256), (100_000, 128, 32_768)])
+@pytest.mark.parametrize("m,n,s1", [(2_100_001, 8, 128), (600_000, 16, 256), (100_000, 128, 32_768), (150_000, 128, 32_769)])
 def test_w1_integer_bit_exact_fp32_sketch(m, n, s1):
     # |bucket sums| <= rows_per_bucket * bound < 2^24 keeps every FP32 partial sum exact
     say("countsketch path fp32", m, n, s1)
