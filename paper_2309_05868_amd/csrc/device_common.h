@@ -73,6 +73,9 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Upper 16x16 block (a, b), a <= b, of an nb x nb block grid, numbered row by row.
+__host__ __device__ constexpr int upper_blk(int a, int b, int nb) { return a * nb - a * (a - 1) / 2 + (b - a); }
+
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 
 __device__ __forceinline__ double shfl_xor_d(double v, int mask) { return __shfl_xor(v, mask, kWave); }

@@ -215,13 +215,20 @@ hipError_t launch_apply_rinv(int np, double* Q, int64_t m, int n, int64_t ldq, c
 // In a batch the input rows are the member's V, or its Q when src_q; the output is its Q.
 hipError_t launch_solve128(const double* in, int64_t m, int n, int64_t ldin, const double* rbk, const int32_t* info, double* out,
                            int64_t ldout, hipStream_t s, int grid_mult = 2, const MemberStride& ms = MemberStride(), int src_q = 0);
+// The Gram phase's solve: Q0 = V R^{-1} into Q (Q may alias V), x_lo by the 64-column Gram pass,
+// which also writes the Gram partials of columns 0..63 (gram_blocks(m) compact partials of 10
+// blocks) to gplo for launch_syrk128.
+hipError_t launch_solve128_gram(const double* V, int64_t m, int n, int64_t ldv, const double* rbk, const int32_t* info, double* Q,
+                                int64_t ldq, double* gplo, hipStream_t s, int grid_mult = 2, const MemberStride& ms = MemberStride());
 // R1^{-1} of a blocked packed factor as the 36 upper 16 x 16 blocks (rinv: 36 * 256 doubles), and
 // Q = Q0 R1^{-1} in place on the stored Q0 from them (65..128 columns).
 hipError_t launch_rinv128(const double* rbk, const int32_t* info, double* rinv, hipStream_t s, const MemberStride& ms = MemberStride());
 hipError_t launch_apply_rinv128(double* Q, int64_t m, int n, int64_t ldq, const double* rinv, const int32_t* info, int grid_mult,
                                 hipStream_t s, const MemberStride& ms = MemberStride());
-// Gram partials of Q0 (kGramBlocks compact partials of 36 upper 16x16 blocks).
-hipError_t launch_syrk128(const double* Q0, int64_t m, int n, int64_t ldq, const int32_t* info, double* gpart, hipStream_t s,
-                          const MemberStride& ms = MemberStride());
+// Gram partials of Q0 (kGramBlocks compact partials of 36 upper 16x16 blocks): the blocks that
+// involve columns 64..127 from Q0, those of columns 0..63 copied from the nblo partials in gplo
+// (launch_solve128_gram's; a ragged member's count is its own Gram grid).
+hipError_t launch_syrk128(const double* Q0, int64_t m, int n, int64_t ldq, const int32_t* info, double* gpart, const double* gplo,
+                          int64_t nblo, hipStream_t s, const MemberStride& ms = MemberStride());
 
 }  // namespace rcqr

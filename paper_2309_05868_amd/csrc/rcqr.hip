@@ -31,7 +31,7 @@ int padded_cols(int64_t n) {
 }
 
 struct Layout {
-  size_t info, minfo, w1, csparts, codes, counts, offsets, hist, entries, unsorted, wpart, w, qra, qrb, r0, r0pk, gpart, gc, g, r1, r1pk,
+  size_t info, minfo, w1, csparts, codes, counts, offsets, hist, entries, unsorted, wpart, w, qra, qrb, r0, r0pk, gpart, gplo, gc, g, r1, r1pk,
       ra, rapk, rtmp, rtmp2, rinv, total;
 };
 
@@ -101,6 +101,7 @@ Layout make_layout(const Shape& sh) {
   L.r0 = take(n * n * 8);
   L.r0pk = take(pk);
   L.gpart = take((size_t)kGramBlocks * gram_compact_len((int)np) * 8);
+  L.gplo = take(np > 64 ? (size_t)kGramBlocks * gram_compact_len(64) * 8 : 0);  // Gram partials of columns 0..63
   L.gc = take((size_t)gram_compact_len((int)np) * 8);
   L.g = take(n * n * 8);
   L.r1 = take(n * n * 8);
@@ -307,8 +308,9 @@ static rcqr_status_t run_gram(rcqr_plan_t p, const double* V, int64_t ldv, const
     RCQR_TRY(launch_trsm_gram(sh.np, V, sh.m, (int)sh.n, ldv, rpk, info, p->at<double>(p->L.gpart), store_q0 ? Q : nullptr,
                               store_q0 ? ldq : 0, p->stream));
   } else {
-    RCQR_TRY(launch_solve128(V, sh.m, (int)sh.n, ldv, rpk, info, Q, ldq, p->stream, p->grid_mult));
-    RCQR_TRY(launch_syrk128(Q, sh.m, (int)sh.n, ldq, info, p->at<double>(p->L.gpart), p->stream));
+    RCQR_TRY(launch_solve128_gram(V, sh.m, (int)sh.n, ldv, rpk, info, Q, ldq, p->at<double>(p->L.gplo), p->stream, p->grid_mult));
+    RCQR_TRY(launch_syrk128(Q, sh.m, (int)sh.n, ldq, info, p->at<double>(p->L.gpart), p->at<double>(p->L.gplo), gram_blocks(sh.m),
+                            p->stream));
   }
   const int nparts = sh.np <= 64 ? gram_blocks(sh.m) : kGramBlocks;  // the 65-128-column Gram keeps the full grid
   RCQR_TRY(launch_reduce_parts(p->at<double>(p->L.gpart), nparts, len, len, p->at<double>(p->L.gc), p->stream));
@@ -564,8 +566,8 @@ static rcqr_status_t run_batch(rcqr_plan_t p, const MemberStride& ms, const doub
     RCQR_TRY(launch_trsm_gram(sh.np, V, sh.m, n, ldv, p->at<double>(L.r0pk), info, p->at<double>(L.gpart), nullptr, ldq, s, ms));
     RCQR_TRY(launch_reduce_parts(p->at<double>(L.gpart), gram_blocks(sh.m), len, len, p->at<double>(L.gc), s, ms, kPartsGram));
   } else {
-    RCQR_TRY(launch_solve128(V, sh.m, n, ldv, p->at<double>(L.r0pk), info, Q, ldq, s, p->grid_mult, ms, 0));
-    RCQR_TRY(launch_syrk128(Q, sh.m, n, ldq, info, p->at<double>(L.gpart), s, ms));
+    RCQR_TRY(launch_solve128_gram(V, sh.m, n, ldv, p->at<double>(L.r0pk), info, Q, ldq, p->at<double>(L.gplo), s, p->grid_mult, ms));
+    RCQR_TRY(launch_syrk128(Q, sh.m, n, ldq, info, p->at<double>(L.gpart), p->at<double>(L.gplo), gram_blocks(sh.m), s, ms));
     RCQR_TRY(launch_reduce_parts(p->at<double>(L.gpart), kGramBlocks, len, len, p->at<double>(L.gc), s, ms));
   }
   // Algorithm 2, step 2 and Algorithm 3, step 3: R1 = chol(G), R = R1 R0
@@ -1064,9 +1066,11 @@ rcqr_status_t rcqr_q0_twice(rcqr_plan_t p, const double* V, int64_t ldv, double*
     RCQR_TRY(launch_identity_factor((int)sh.n, sh.np, p->at<double>(L.ra), p->at<double>(L.rapk), p->stream));
     RCQR_TRY(launch_final(sh.np, true, V, sh.m, (int)sh.n, ldv, p->at<double>(L.r0pk), p->at<double>(L.rapk),
                           p->at<int32_t>(L.info), Q0b, ldq, p->stream, p->grid_mult));
-  } else {  // Q0 is stored, not recomputed: both outputs come from the same solve
-    RCQR_TRY(launch_solve128(V, sh.m, (int)sh.n, ldv, p->at<double>(L.r0pk), p->at<int32_t>(L.info), Q0a, ldq, p->stream));
-    RCQR_TRY(launch_solve128(V, sh.m, (int)sh.n, ldv, p->at<double>(L.r0pk), p->at<int32_t>(L.info), Q0b, ldq, p->stream));
+  } else {  // Q0 is stored, not recomputed: both outputs come from the Gram phase's solve
+    RCQR_TRY(launch_solve128_gram(V, sh.m, (int)sh.n, ldv, p->at<double>(L.r0pk), p->at<int32_t>(L.info), Q0a, ldq,
+                                  p->at<double>(L.gplo), p->stream));
+    RCQR_TRY(launch_solve128_gram(V, sh.m, (int)sh.n, ldv, p->at<double>(L.r0pk), p->at<int32_t>(L.info), Q0b, ldq,
+                                  p->at<double>(L.gplo), p->stream));
   }
   return RCQR_OK;
 }

@@ -274,9 +274,6 @@ __global__ __launch_bounds__(NW * kWave) void final_kernel(const double* __restr
   }
 }
 
-// Upper 16x16 block (a, b), a <= b, of an NB x NB block grid, numbered row by row.
-__device__ __forceinline__ int upper_blk(int a, int b, int nb) { return a * nb - a * (a - 1) / 2 + (b - a); }
-
 // Row i of R^{-1} in lane i (x R = e_i by the row substitution), stored as the upper 16 x 16
 // blocks of R^{-1} (row-major blocks, upper_blk order) in rib.  One wave.
 template <int NP>
@@ -836,14 +833,9 @@ hipError_t launch_apply_rinv(int np, double* Q, int64_t m, int n, int64_t ldq, c
   return hipGetLastError();
 }
 
-hipError_t launch_solve128(const double* in, int64_t m, int n, int64_t ldin, const double* rbk, const int32_t* info, double* out,
-                           int64_t ldout, hipStream_t s, int grid_mult, const MemberStride& ms, int src_q) {
-  if (m <= 0) return hipSuccess;
-  if (n <= 64 || n > 128 || ms.count < 1) return hipErrorInvalidValue;
-  // x_lo = v_lo R00^{-1} into the output's first 64 columns (R00 packed leads the blocked format);
-  // the 64-column view of 16-byte aligned rows with even leading dimensions is aligned too
-  const hipError_t e = launch_final(64, false, in, m, 64, ldin, rbk, rbk, info, out, ldout, s, 2, ms, src_q);
-  if (e != hipSuccess) return e;
+// x_hi = (v_hi - x_lo R01) R11^{-1} for x_lo already in the output's first 64 columns.
+static hipError_t launch_solve_hi(const double* in, int64_t m, int n, int64_t ldin, const double* rbk, const int32_t* info,
+                                  double* out, int64_t ldout, hipStream_t s, int grid_mult, const MemberStride& ms, int src_q) {
   constexpr int NW = 8;
   const int64_t tiles = (m + kWave - 1) / kWave;
   int64_t g = (tiles + NW - 1) / NW;
@@ -860,6 +852,28 @@ hipError_t launch_solve128(const double* in, int64_t m, int n, int64_t ldin, con
   }
 #undef RCQR_HI
   return hipGetLastError();
+}
+
+hipError_t launch_solve128(const double* in, int64_t m, int n, int64_t ldin, const double* rbk, const int32_t* info, double* out,
+                           int64_t ldout, hipStream_t s, int grid_mult, const MemberStride& ms, int src_q) {
+  if (m <= 0) return hipSuccess;
+  if (n <= 64 || n > 128 || ms.count < 1) return hipErrorInvalidValue;
+  // x_lo = v_lo R00^{-1} into the output's first 64 columns (R00 packed leads the blocked format);
+  // the 64-column view of 16-byte aligned rows with even leading dimensions is aligned too
+  const hipError_t e = launch_final(64, false, in, m, 64, ldin, rbk, rbk, info, out, ldout, s, 2, ms, src_q);
+  if (e != hipSuccess) return e;
+  return launch_solve_hi(in, m, n, ldin, rbk, info, out, ldout, s, grid_mult, ms, src_q);
+}
+
+hipError_t launch_solve128_gram(const double* V, int64_t m, int n, int64_t ldv, const double* rbk, const int32_t* info, double* Q,
+                                int64_t ldq, double* gplo, hipStream_t s, int grid_mult, const MemberStride& ms) {
+  if (m <= 0) return hipSuccess;
+  if (n <= 64 || n > 128 || ms.count < 1) return hipErrorInvalidValue;
+  // x_lo by the 64-column Gram pass (R00 packed leads the blocked format), stored in Q's first 64
+  // columns, with the Gram blocks of those columns into gplo
+  const hipError_t e = launch_trsm_gram(64, V, m, 64, ldv, rbk, info, gplo, Q, ldq, s, ms);
+  if (e != hipSuccess) return e;
+  return launch_solve_hi(V, m, n, ldv, rbk, info, Q, ldq, s, grid_mult, ms, 0);
 }
 
 }  // namespace rcqr

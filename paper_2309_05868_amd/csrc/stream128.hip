@@ -7,11 +7,14 @@ namespace rcqr {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-// G partial = Q0^T Q0 over this workgroup's rows: the 36 upper 16x16 blocks of the 128 x 128
-// matrix on FP64 MFMA.  Four wave pairs per workgroup; waves 2p and 2p+1 read the same 4-row
-// K-steps and accumulate blocks 0..17 and 18..35 respectively (144 accumulator registers
-// each).  The operands of the next kSyrkAhead K-steps are in flight while a step's MFMAs run.
-// Fixed grid, fixed order.
+// G partial = Q0^T Q0 over this workgroup's rows on FP64 MFMA, in the 36 upper 16x16 blocks of
+// the 128 x 128 matrix.  This kernel forms the 26 blocks that involve columns 64..127; the 10
+// blocks of columns 0..63 come from the pass that solved those columns (the 64-column Gram pass,
+// which stores x_lo): workgroup b copies that pass's partial b into its slots (zeros past its
+// grid), so one fixed-order reduction over the partials still gives G.  Four wave pairs per
+// workgroup; waves 2p and 2p+1 read the same 4-row K-steps and accumulate 13 blocks each.  The
+// operands of the next kSyrkAhead K-steps are in flight while a step's MFMAs run.  Fixed grid,
+// fixed order.
 constexpr int kSyrkPairs = 4;
 constexpr int kSyrkAhead = 3;  // K-steps whose operands are loaded ahead of use
 
@@ -28,18 +31,23 @@ __device__ __forceinline__ void syrk_operands(double (&F)[8], const double* __re
 template <bool FULL, bool BATCH>
 __global__ __launch_bounds__(2 * kSyrkPairs * kWave) void syrk128_kernel(const double* __restrict__ Q0, int64_t m, int n, int64_t ldq,
                                                                        const int32_t* __restrict__ info, double* __restrict__ gpart,
+                                                                       const double* __restrict__ gplo, int64_t nblo,
                                                                        MemberStride ms) {
-  constexpr int NB = 8, NBU = NB * (NB + 1) / 2, HALF = NBU / 2;  // 36 blocks, 18 per wave
+  constexpr int NB = 8, NBU = NB * (NB + 1) / 2;  // 36 upper blocks
+  constexpr int NL = 4, NLU = NL * (NL + 1) / 2;  // 10 of them within columns 0..63
+  constexpr int HALF = (NBU - NLU) / 2;           // 13 blocks per wave
   __shared__ double gl[NBU * 256];
   if constexpr (BATCH) {  // batch member: its stored Q0 (in its Q) and workspace slice
     const int64_t mb = blockIdx.y, off = mb * ms.ws;
     info += off / (int64_t)sizeof(int32_t);
     gpart += off / (int64_t)sizeof(double);
+    gplo += off / (int64_t)sizeof(double);
     if (ms.info != nullptr) {
       const MemberInfo& mi = member_info(ms, mb);
       Q0 = mi.Q;
       ldq = mi.ldq;
       m = mi.m;
+      nblo = mi.gblocks;
     } else {
       Q0 += mb * ms.q;
     }
@@ -47,6 +55,16 @@ __global__ __launch_bounds__(2 * kSyrkPairs * kWave) void syrk128_kernel(const d
   if (info[0] != 0) return;
   const int wave = threadIdx.x / kWave, lane = lane_id();
   const int set = wave & 1, pair = wave >> 1;
+  {  // the blocks of columns 0..63: this workgroup's partial from the 64-column pass
+    const bool have = (int64_t)blockIdx.x < nblo;
+    const double* src = gplo + (int64_t)blockIdx.x * (NLU * 256);
+    for (int i = threadIdx.x; i < NLU * 256; i += 2 * kSyrkPairs * kWave) {
+      const int k = i / 256;
+      const int a = k < 4 ? 0 : (k < 7 ? 1 : (k < 9 ? 2 : 3));
+      const int b = a + (k - upper_blk(a, a, NL));
+      gl[upper_blk(a, b, NB) * 256 + (i & 255)] = have ? src[i] : 0.0;
+    }
+  }
   d4 acc[HALF];
 #pragma unroll
   for (int i = 0; i < HALF; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
@@ -70,7 +88,7 @@ __global__ __launch_bounds__(2 * kSyrkPairs * kWave) void syrk128_kernel(const d
 #pragma unroll
       for (int a = 0; a < NB; ++a) {
 #pragma unroll
-        for (int b = a; b < NB; ++b) {
+        for (int b = a < NL ? NL : a; b < NB; ++b) {
           if (set == 0 && ab < HALF) acc[ab] = __builtin_amdgcn_mfma_f64_16x16x4f64(F[a], F[b], acc[ab], 0, 0, 0);
           if (set == 1 && ab >= HALF) acc[ab - HALF] = __builtin_amdgcn_mfma_f64_16x16x4f64(F[a], F[b], acc[ab - HALF], 0, 0, 0);
           ++ab;
@@ -79,15 +97,24 @@ __global__ __launch_bounds__(2 * kSyrkPairs * kWave) void syrk128_kernel(const d
     }
   }
   // fixed-order sum over the pairs; element e of lane l is D[l/16 + 4e][l%16]
+  __syncthreads();
   for (int p = 0; p < kSyrkPairs; ++p) {
     if (pair == p) {
-#pragma unroll
-      for (int i = 0; i < HALF; ++i) {
-        const int ab = set * HALF + i;
+      auto put = [&](int blk, const d4& v) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int idx = ab * 256 + ((lane >> 4) + 4 * e) * 16 + (lane & 15);
-          gl[idx] = (p == 0) ? acc[i][e] : gl[idx] + acc[i][e];
+          const int idx = blk * 256 + ((lane >> 4) + 4 * e) * 16 + (lane & 15);
+          gl[idx] = (p == 0) ? v[e] : gl[idx] + v[e];
+        }
+      };
+      int ab = 0;
+#pragma unroll
+      for (int a = 0; a < NB; ++a) {
+#pragma unroll
+        for (int b = a < NL ? NL : a; b < NB; ++b) {
+          if (set == 0 && ab < HALF) put(upper_blk(a, b, NB), acc[ab]);
+          if (set == 1 && ab >= HALF) put(upper_blk(a, b, NB), acc[ab - HALF]);
+          ++ab;
         }
       }
     }
@@ -97,21 +124,21 @@ __global__ __launch_bounds__(2 * kSyrkPairs * kWave) void syrk128_kernel(const d
   for (int i = threadIdx.x; i < NBU * 256; i += 2 * kSyrkPairs * kWave) outp[i] = gl[i];
 }
 
-hipError_t launch_syrk128(const double* Q0, int64_t m, int n, int64_t ldq, const int32_t* info, double* gpart, hipStream_t s,
-                          const MemberStride& ms) {
+hipError_t launch_syrk128(const double* Q0, int64_t m, int n, int64_t ldq, const int32_t* info, double* gpart, const double* gplo,
+                          int64_t nblo, hipStream_t s, const MemberStride& ms) {
   if (ms.count < 1) return hipErrorInvalidValue;
   const dim3 grid(kGramBlocks, ms.count), block(2 * kSyrkPairs * kWave);
   const bool batch = ms.count > 1 || ms.info != nullptr;
   if (batch) {
     if (n == 128)
-      hipLaunchKernelGGL((syrk128_kernel<true, true>), grid, block, 0, s, Q0, m, n, ldq, info, gpart, ms);
+      hipLaunchKernelGGL((syrk128_kernel<true, true>), grid, block, 0, s, Q0, m, n, ldq, info, gpart, gplo, nblo, ms);
     else
-      hipLaunchKernelGGL((syrk128_kernel<false, true>), grid, block, 0, s, Q0, m, n, ldq, info, gpart, ms);
+      hipLaunchKernelGGL((syrk128_kernel<false, true>), grid, block, 0, s, Q0, m, n, ldq, info, gpart, gplo, nblo, ms);
   } else {
     if (n == 128)
-      hipLaunchKernelGGL((syrk128_kernel<true, false>), grid, block, 0, s, Q0, m, n, ldq, info, gpart, ms);
+      hipLaunchKernelGGL((syrk128_kernel<true, false>), grid, block, 0, s, Q0, m, n, ldq, info, gpart, gplo, nblo, ms);
     else
-      hipLaunchKernelGGL((syrk128_kernel<false, false>), grid, block, 0, s, Q0, m, n, ldq, info, gpart, ms);
+      hipLaunchKernelGGL((syrk128_kernel<false, false>), grid, block, 0, s, Q0, m, n, ldq, info, gpart, gplo, nblo, ms);
   }
   return hipGetLastError();
 }
