@@ -16,7 +16,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // operands of the next kSyrkAhead K-steps are in flight while a step's MFMAs run.  Fixed grid,
 // fixed order.
 constexpr int kSyrkPairs = 4;
-constexpr int kSyrkAhead = 3;  // K-steps whose operands are loaded ahead of use
+constexpr int kSyrkAhead = 5;  // K-steps whose operands are loaded ahead of use
 
 template <bool FULL>
 __device__ __forceinline__ void syrk_operands(double (&F)[8], const double* __restrict__ Q0, int64_t row, int64_t m, int n,
