@@ -540,11 +540,16 @@ __global__ __launch_bounds__(NW * kWave) void apply_rinv_kernel(double* Q, int64
 // Q = Q0 R1^{-1} as one product on the matrix cores over the stored Q0 (apply_rinv128_kernel).
 // Row i of R^{-1} solves x R = e_i by block substitution over the blocked factor
 // [R00 | R01; 0 | R11]: x_lo = e_i R00^{-1} (zero below row 64), x_hi = (e_i,hi - x_lo R01) R11^{-1};
-// lane i of wave 0 takes rows 0..63, lane i of wave 1 rows 64..127.  The upper 16 x 16 blocks
-// of R^{-1} (36 of them, row-major blocks in upper_blk order) go to rinv.
-__global__ __launch_bounds__(2 * kWave) void rinv128_kernel(const double* __restrict__ Rbk, const int32_t* __restrict__ info,
-                                                           double* __restrict__ rinv, MemberStride ms) {
+// lane i of wave 0 takes rows 0..63, lane i of wave 1 rows 64..127 (x_lo = 0, so x_hi = e_i R11^{-1}
+// at once, while wave 0 solves with R00).  The coupling product x_lo R01 (64 x 64 x 64) runs on the
+// matrix cores, one 16-row block per wave, with x_lo and R01 staged in LDS.  The upper 16 x 16
+// blocks of R^{-1} (36 of them, row-major blocks in upper_blk order) go to rinv.
+constexpr int kRinvWaves = 4;
+__global__ __launch_bounds__(kRinvWaves * kWave) void rinv128_kernel(const double* __restrict__ Rbk, const int32_t* __restrict__ info,
+                                                                    double* __restrict__ rinv, MemberStride ms) {
   constexpr int H = 64, PK = H * (H + 1) / 2, NB = 8;
+  __shared__ double r01[H][H + 1];
+  __shared__ double xs[H][H + 1];  // x_lo of rows 0..63, then x_lo R01
   {
     const int64_t off = (int64_t)blockIdx.y * ms.ws;  // batch member
     Rbk += off / (int64_t)sizeof(double);
@@ -553,25 +558,48 @@ __global__ __launch_bounds__(2 * kWave) void rinv128_kernel(const double* __rest
   }
   if (info[0] != 0) return;
   const int wave = threadIdx.x / kWave, lane = lane_id();
+  const int li = lane & 15, lq = lane >> 4;
+  for (int i = threadIdx.x; i < H * H; i += kRinvWaves * kWave) r01[i / H][i % H] = Rbk[PK + i];
   const int row = wave * H + lane;
   double lo[H], hi[H];
+  if (wave < 2) {
 #pragma unroll
-  for (int c = 0; c < H; ++c) {
-    lo[c] = (wave == 0 && c == lane) ? 1.0 : 0.0;
-    hi[c] = (wave == 1 && c == lane) ? 1.0 : 0.0;
-  }
-  if (wave == 0) {
-    rowsolve<H>(lo, Rbk);
-    // hi -= lo R01 (R01 dense 64 x 64 row-major after R00's packed triangle); k ascending
-    const double* __restrict__ R01 = Rbk + PK;
+    for (int c = 0; c < H; ++c) {
+      lo[c] = (wave == 0 && c == lane) ? 1.0 : 0.0;
+      hi[c] = (wave == 1 && c == lane) ? 1.0 : 0.0;
+    }
+    if (wave == 0) {
+      rowsolve<H>(lo, Rbk);
 #pragma unroll
-    for (int k = 0; k < H; ++k) {
-      const double xk = lo[k];
-#pragma unroll
-      for (int j = 0; j < H; ++j) hi[j] = __builtin_fma(-xk, R01[k * H + j], hi[j]);
+      for (int c = 0; c < H; ++c) xs[lane][c] = lo[c];
+    } else {
+      rowsolve<H>(hi, Rbk + PK + H * H);
     }
   }
-  rowsolve<H>(hi, Rbk + PK + H * H);
+  __syncthreads();
+  // x_lo R01, rows 16 w .. 16 w + 15 by wave w; element e of lane l: row 16 w + l/16 + 4e,
+  // column 16 cb + l%16
+  d4 acc[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ks = 0; ks < H / 4; ++ks) {
+    const double a = xs[16 * wave + li][4 * ks + lq];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, r01[4 * ks + lq][16 * cb + li], acc[cb], 0, 0, 0);
+  }
+  __syncthreads();  // every wave has read its x_lo operands
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) xs[16 * wave + lq + 4 * e][16 * cb + li] = acc[cb][e];
+  __syncthreads();
+  if (wave >= 2) return;
+  if (wave == 0) {
+#pragma unroll
+    for (int c = 0; c < H; ++c) hi[c] = -xs[lane][c];
+    rowsolve<H>(hi, Rbk + PK + H * H);
+  }
   const int a = row / 16;
 #pragma unroll
   for (int cb = 0; cb < NB; ++cb) {
@@ -667,7 +695,7 @@ static int final_grid();
 
 hipError_t launch_rinv128(const double* rbk, const int32_t* info, double* rinv, hipStream_t s, const MemberStride& ms) {
   if (ms.count < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(rinv128_kernel, dim3(1, ms.count), dim3(2 * kWave), 0, s, rbk, info, rinv, ms);
+  hipLaunchKernelGGL(rinv128_kernel, dim3(1, ms.count), dim3(kRinvWaves * kWave), 0, s, rbk, info, rinv, ms);
   return hipGetLastError();
 }
 
