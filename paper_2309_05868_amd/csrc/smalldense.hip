@@ -386,7 +386,7 @@ __device__ __forceinline__ int upper_block_index(int a, int b, int nb) {
 // the end for all rows at once.
 template <int NP>
 struct CholShape {
-  static constexpr int NWV = NP == 64 ? 16 : (NP > 64 ? 8 : 4);  // waves (one 4-row block per wave at 64)
+  static constexpr int NWV = NP >= 64 ? 16 : 4;  // waves (one 4-row block per wave at 64, two at 128)
   static constexpr int CPL = NP > 64 ? 2 : 1;   // columns per lane
   static constexpr int BR = 4;                  // rows per block
   static constexpr int NBT = NP / (NWV * BR);   // row blocks per thread
