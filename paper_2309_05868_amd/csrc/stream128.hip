@@ -18,13 +18,15 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kSyrkPairs = 4;
 constexpr int kSyrkAhead = 5;  // K-steps whose operands are loaded ahead of use
 
+// Operands of one 4-row K-step: F[a] = Q0[row][16 a + csub] for the column blocks a >= a0 this
+// wave multiplies (the others are not loaded).
 template <bool FULL>
 __device__ __forceinline__ void syrk_operands(double (&F)[8], const double* __restrict__ Q0, int64_t row, int64_t m, int n,
-                                              int64_t ldq, int csub) {
+                                              int64_t ldq, int csub, int a0) {
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
     const int c = 16 * a + csub;
-    F[a] = (row < m && (FULL || c < n)) ? Q0[row * ldq + c] : 0.0;
+    F[a] = (a >= a0 && row < m && (FULL || c < n)) ? Q0[row * ldq + c] : 0.0;
   }
 }
 
@@ -74,16 +76,18 @@ __global__ __launch_bounds__(2 * kSyrkPairs * kWave) void syrk128_kernel(const d
   int64_t st = (int64_t)blockIdx.x * kSyrkPairs + pair;
   // operands of the next kSyrkAhead K-steps in flight (a ring, unrolled so every index is fixed);
   // steps at or past nsteps read rows past m, which load as zeros and add exact zeros
+  // set 0 multiplies column blocks 0..7 (blocks (0..2, 4..7) and (3, 4)), set 1 blocks 3..7
+  const int a0 = set == 0 ? 0 : 3;
   double Fq[kSyrkAhead][NB];
 #pragma unroll
-  for (int k = 0; k < kSyrkAhead; ++k) syrk_operands<FULL>(Fq[k], Q0, 4 * (st + k * stride) + rsub, m, n, ldq, csub);
+  for (int k = 0; k < kSyrkAhead; ++k) syrk_operands<FULL>(Fq[k], Q0, 4 * (st + k * stride) + rsub, m, n, ldq, csub, a0);
   for (; st < nsteps; st += kSyrkAhead * stride) {
 #pragma unroll
     for (int k = 0; k < kSyrkAhead; ++k) {
       double F[NB];
 #pragma unroll
       for (int a = 0; a < NB; ++a) F[a] = Fq[k][a];
-      syrk_operands<FULL>(Fq[k], Q0, 4 * (st + (k + kSyrkAhead) * stride) + rsub, m, n, ldq, csub);
+      syrk_operands<FULL>(Fq[k], Q0, 4 * (st + (k + kSyrkAhead) * stride) + rsub, m, n, ldq, csub, a0);
       int ab = 0;
 #pragma unroll
       for (int a = 0; a < NB; ++a) {
