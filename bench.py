@@ -258,16 +258,36 @@ def serve_c4(args, dev):
     be = srv.GpuBackend(get_V, args.serve_slots, device=dev, batch_hint=1, m_cap=m_cap, batching=False)
     srv.serve(reqs[:512], get_V, slots=args.serve_slots, budget_bytes=budget, max_batch=1, backend=be)
     be.close()
+    # accuracy is checked on the served Q and R of a sample of requests (m <= 5e5, which bounds the
+    # memory the kept outputs hold) from the continuous-batching run
+    rng = np.random.Generator(np.random.PCG64(9))
+    small = [i for i, r in enumerate(reqs) if r["m"] <= 500_000]
+    sample = [reqs[int(i)] for i in rng.choice(small, size=min(32, len(small)), replace=False)]
+    sample_seeds = {r["seed"] for r in sample}
+    worst, checked = 0.0, 0
     out = {}
     for name, slots, max_batch, batching in modes:
         # one cached plan per column shape and slot (no plan churn), sized for a few members at m_cap
         # rows and remade larger only when a bigger batch forms
+        keep = sample_seeds if name == "continuous_batching" else False
         be = srv.GpuBackend(get_V, slots, device=dev, batch_hint=min(max_batch, 4), m_cap=m_cap, batching=batching,
-                            plans_per_slot=len(wl["n_choices"]))
+                            plans_per_slot=len(wl["n_choices"]), keep_outputs=keep)
         warm = [dict(r, arrival_s=0.0) for r in reqs[:64]]
         srv.serve(warm, get_V, slots=slots, budget_bytes=budget, max_batch=max_batch, backend=be)
         log(f"bench: serving {len(reqs)} requests, {name} ({slots} stream(s), batches of up to {max_batch})")
         run, summary, _ = srv.serve(reqs, get_V, slots=slots, budget_bytes=budget, max_batch=max_batch, backend=be)
+        if keep:
+            torch.cuda.synchronize()
+            for r in sample:
+                Q, R = be.outputs[r["seed"]]
+                V = get_V(r)
+                n = r["n"]
+                eye = torch.eye(n, dtype=torch.float64, device=dev)
+                orth = torch.linalg.norm(eye - gram_accurate(Q)).item()
+                res = (torch.linalg.norm(V - Q @ R) / torch.linalg.norm(V)).item()
+                worst = max(worst, orth / (10 * n * U_PAPER), res / (10 * n * U_PAPER))
+                checked += 1
+            be.outputs.clear()
         be.close()
         summary["slots"] = slots
         summary["max_batch"] = max_batch
@@ -275,19 +295,6 @@ def serve_c4(args, dev):
                                       max(1, sum(1 for r in run["results"] if r and r.get("batch"))), 2)
         out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summary.items()}
     warm = reqs[:64]
-    # accuracy of a sample of requests (each factored alone)
-    rng = np.random.Generator(np.random.PCG64(9))
-    worst = 0.0
-    for i in rng.choice(len(reqs), size=32, replace=False):
-        r = reqs[int(i)]
-        V = get_V(r)
-        with rc.Plan(r["m"], r["n"], r["s1"], r["s2"], r["seed"], device=dev) as p:
-            Q, R = p.factor(V)
-        n = r["n"]
-        eye = torch.eye(n, dtype=torch.float64, device=dev)
-        orth = torch.linalg.norm(eye - gram_accurate(Q)).item()
-        res = (torch.linalg.norm(V - Q @ R) / torch.linalg.norm(V)).item()
-        worst = max(worst, orth / (10 * n * U_PAPER), res / (10 * n * U_PAPER))
     del bank
     torch.cuda.empty_cache()
     workload = (f"rand_cholQR serving: {wl['count']} requests, Poisson {wl['rate_per_s']:.0f}/s, m log-uniform "
@@ -295,8 +302,9 @@ def serve_c4(args, dev):
                 f"[{wl['kappa_range'][0]:.0e}, {wl['kappa_range'][1]:.0e}], s1 = 2n^2, s2 = 4n")
     note = (f"V = leading m rows of a device-resident base U diag(sigma) W^T per n with the nearest of "
             f"{len(SERVE_KAPPA_BANK)} log-spaced kappa values; latency = device completion - arrival")
-    return {"workload": workload, "modes": out, "sample_worst_error_over_10nu": worst, "note": note,
-            "warmup_requests": len(warm)}
+    return {"workload": workload, "modes": out, "sample_worst_error_over_10nu": worst, "sample_checked": checked,
+            "sample": "served Q and R of 32 requests with m <= 5e5 from the continuous-batching run",
+            "note": note, "warmup_requests": len(warm)}
 
 
 def serve_workload(args):
@@ -309,7 +317,8 @@ def serve_workload(args):
         "steps": SERVE_WORKLOAD["count"], "warmup": res["warmup_requests"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": {"workload": res["workload"]},
         "p50_ms": cb.get("p50_ms"), "p99_ms": cb.get("p99_ms"), "modes": res["modes"],
-        "sample_worst_error_over_10nu": res["sample_worst_error_over_10nu"], "note": res["note"],
+        "sample_worst_error_over_10nu": res["sample_worst_error_over_10nu"], "sample": res["sample"],
+        "sample_checked": res["sample_checked"], "note": res["note"],
     }
     print(json.dumps(line), flush=True)
 
@@ -912,6 +921,7 @@ def main():
         out["served"] = {"workload": sv["workload"], "p50_ms": cb.get("p50_ms"), "p99_ms": cb.get("p99_ms"),
                          "qr_per_s": cb.get("qr_per_s"), "one_at_a_time": {k: one.get(k) for k in ("p50_ms", "p99_ms", "qr_per_s")},
                          "continuous_batching": cb, "sample_worst_error_over_10nu": sv["sample_worst_error_over_10nu"],
+                         "sample_checked": sv["sample_checked"],
                          "note": sv["note"]}
     if not args.no_cpu_baseline:
         log(f"bench: cpu baseline on {args.cpu_sample_rows} rows")

@@ -190,7 +190,7 @@ class GpuBackend:
         self.m_cap = int(m_cap)
         self.get_V = get_V
         self.flags = flags
-        self.keep = keep_outputs
+        self.keep = keep_outputs  # True: every request's (Q, R) by seed; a set of seeds: those requests' only
         self.streams = [torch.cuda.Stream(self.device) for _ in range(slots)]
         self.busy = set()  # slots with a launch in flight
         self.outputs = {}
@@ -309,6 +309,9 @@ class GpuBackend:
             done.record(stream)
         return {"reqs": reqs, "plan": plan, "Q": Qs, "R": Rs, "V": Vs, "event": done, "slot": slot}
 
+    def _kept(self, seed):
+        return self.keep is True or (not isinstance(self.keep, bool) and seed in self.keep)
+
     def poll(self, handle):
         if not handle["event"].query():
             return None
@@ -316,12 +319,12 @@ class GpuBackend:
         self.busy.discard(handle["slot"])
         if "reqs" in handle:  # a batch (its plan stays cached for the slot)
             sts = [st for st, _ in handle["plan"].info_batch(len(handle["reqs"]))]
-            if self.keep:
-                for b, r in enumerate(handle["reqs"]):
+            for b, r in enumerate(handle["reqs"]):
+                if self._kept(r["seed"]):
                     self.outputs[r["seed"]] = (handle["Q"][b], handle["R"][b])
             return end, sts
         st, _ = handle["plan"].info()
-        if self.keep:
+        if self._kept(handle["req"]["seed"]):
             self.outputs[handle["req"]["seed"]] = (handle["Q"], handle["R"])
         handle["plan"].close()
         return end, st
