@@ -376,7 +376,9 @@ __global__ __launch_bounds__(NW * kWave) void final_mfma_kernel(const double* __
 // 65..128 columns: a row does not fit a lane's registers next to the solve's working set, so
 // x R = v runs as a 2 x 2 block substitution over 64-column halves (Section 5.2's row-wise
 // substitution on the diagonal blocks, a product for the coupling block):
-//     x_lo = v_lo R00^{-1}                  final_kernel<64>, written to the output row
+//     x_lo = v_lo R00^{-1}                  written to the output row: in the Gram phase by the
+//                                           64-column Gram pass, which also forms the Gram blocks
+//                                           of columns 0..63; elsewhere by final_kernel<64>
 //     x_hi = (v_hi - x_lo R01) R11^{-1}     solve_hi_kernel
 // The factor is in the blocked packed format [R00 packed | R01 dense row-major | R11 packed]
 // (2080 + 4096 + 2080 doubles).  In solve_hi_kernel the coupling product runs on the matrix
