@@ -237,3 +237,13 @@ def test_serve_rejects_more_slots_than_backend_streams():
     be.streams = [None, None]
     with pytest.raises(ValueError):
         srv.serve([], lambda r: None, slots=3, backend=be)
+
+
+def test_gpu_backend_keeps_outputs_of_selected_seeds():
+    # host logic of output retention: every request's outputs, none, or those of a set of seeds
+    from paper_2309_05868_amd import serve as srv
+
+    be = _fake_backend(srv)
+    for keep, kept in ((True, {1, 2, 3}), (False, set()), ({2, 9}, {2})):
+        be.keep = keep
+        assert {s for s in (1, 2, 3) if be._kept(s)} == kept
