@@ -37,13 +37,14 @@ def solo(V, s1, s2, seed):
 
 
 # (n, s1, s2, row counts): LDS CountSketch (n = 8), bucket index with LDS counters (16, 64),
-# 65..128 columns with the global-counter index and a two-level Householder tree (100, 128)
+# 65..128 columns with the global-counter index and a two-level Householder tree (100, 128; the
+# 140,001-row member fills the whole Gram grid, the others a part of it)
 CLASSES = [
     (8, 128, 32, [5000, 130_001, 64, 20_000]),
     (16, 512, 64, [10_000, 3001, 70_000, 16, 12_345]),
     (64, 8192, 256, [50_000, 20_001, 100, 64]),
     (100, 20_000, 400, [30_000, 7001, 12_000]),
-    (128, 32_768, 512, [20_000, 4097, 9000]),
+    (128, 32_768, 512, [20_000, 4097, 9000, 140_001]),
 ]
 
 
