@@ -199,27 +199,33 @@ hipError_t launch_hash_debug(int64_t row0, int64_t count, int64_t s1, uint64_t s
 // ------------------------------------------------------------------------------------------
 // Bucket index: exclusive scan (one workgroup) and scatter.
 // ------------------------------------------------------------------------------------------
-// Tiles of 8192 counts: each thread scans 8 consecutive counts, the 1024 thread totals are
-// scanned by waves (shuffles) and across the 16 waves through LDS, plus the carry of earlier tiles.
+// Tiles of 1024 x PER counts, moved between memory and LDS by coalesced loads and stores: each
+// thread scans PER consecutive counts from LDS (padded by one word per 32, so the threads of a wave
+// read different banks), the 1024 thread totals are scanned by waves (shuffles) and across the 16
+// waves through LDS, plus the carry of earlier tiles.
+template <int PER>
 __global__ __launch_bounds__(1024) void bucket_scan_kernel(const uint32_t* __restrict__ counts, int64_t s1,
                                                            uint32_t* __restrict__ offsets, uint32_t* __restrict__ cursor,
                                                            int64_t member_bytes) {
-  constexpr int PER = 8;
+  constexpr int TILE = 1024 * PER;
   {
     const int64_t off = (int64_t)blockIdx.y * member_bytes;  // batch member
     counts = member_ptr(counts, off);
     offsets = member_ptr(offsets, off);
     cursor = member_ptr(cursor, off);
   }
+  __shared__ uint32_t tile[TILE + TILE / 32];
   __shared__ uint32_t wsum[16];
   __shared__ uint32_t carry_s;
   const int t = threadIdx.x, lane = lane_id(), wave = t / kWave;
+  auto at = [](int i) { return i + (i >> 5); };
   uint32_t carry = 0;
-  for (int64_t base = 0; base < s1; base += 1024 * PER) {
-    const int64_t i0 = base + (int64_t)t * PER;
+  for (int64_t base = 0; base < s1; base += TILE) {
+    for (int i = t; i < TILE; i += 1024) tile[at(i)] = base + i < s1 ? counts[base + i] : 0u;
+    __syncthreads();
     uint32_t v[PER];
 #pragma unroll
-    for (int u = 0; u < PER; ++u) v[u] = i0 + u < s1 ? counts[i0 + u] : 0u;
+    for (int u = 0; u < PER; ++u) v[u] = tile[at(t * PER + u)];
     uint32_t tot = 0;
 #pragma unroll
     for (int u = 0; u < PER; ++u) tot += v[u];
@@ -231,21 +237,26 @@ __global__ __launch_bounds__(1024) void bucket_scan_kernel(const uint32_t* __res
       if (lane >= off) inc += y;
     }
     if (lane == kWave - 1) wsum[wave] = inc;
-    __syncthreads();
+    __syncthreads();  // every thread has read its counts from the tile
     uint32_t before = carry;
     for (int w = 0; w < wave; ++w) before += wsum[w];
     uint32_t run = before + inc - tot;  // exclusive prefix of this thread's first count
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      if (i0 + u < s1) {
-        offsets[i0 + u] = run;
-        if (cursor) cursor[i0 + u] = run;
-      }
+      tile[at(t * PER + u)] = run;
       run += v[u];
     }
     if (t == 1023) carry_s = run;
     __syncthreads();
     carry = carry_s;
+    for (int i = t; i < TILE; i += 1024) {
+      if (base + i < s1) {
+        const uint32_t o = tile[at(i)];
+        offsets[base + i] = o;
+        if (cursor) cursor[base + i] = o;
+      }
+    }
+    __syncthreads();  // the tile and wsum are reused by the next tile
   }
   if (t == 0) offsets[s1] = carry;
 }
@@ -253,7 +264,12 @@ __global__ __launch_bounds__(1024) void bucket_scan_kernel(const uint32_t* __res
 hipError_t launch_bucket_scan(const uint32_t* counts, int64_t s1, uint32_t* offsets, uint32_t* cursor, hipStream_t s,
                               const MemberStride& ms) {
   if (ms.count < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(bucket_scan_kernel, dim3(1, ms.count), dim3(1024), 0, s, counts, s1, offsets, cursor, ms.ws);
+  // one pass of 1024 x PER buckets at a time: eight per thread up to 8192 buckets, 32 above (one
+  // pass up to 32768; the passes are bound by their shuffles and barriers, not their loads)
+  if (s1 <= 8192)
+    hipLaunchKernelGGL(bucket_scan_kernel<8>, dim3(1, ms.count), dim3(1024), 0, s, counts, s1, offsets, cursor, ms.ws);
+  else
+    hipLaunchKernelGGL(bucket_scan_kernel<32>, dim3(1, ms.count), dim3(1024), 0, s, counts, s1, offsets, cursor, ms.ws);
   return hipGetLastError();
 }
 
