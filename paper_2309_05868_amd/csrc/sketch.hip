@@ -64,7 +64,7 @@ hipError_t launch_fill_f64(double* p, int64_t count, double value, hipStream_t s
 constexpr int kHistLds = 32768;     // buckets counted in LDS by the hash (128 KiB); above this, in the chunk's global row
 constexpr int kScatterLds = 16384;  // buckets whose counters and segment starts the scatter keeps in LDS
 
-__global__ __launch_bounds__(256) void hash_hist_kernel(int64_t m, uint64_t s1, uint64_t seed, int64_t chunk_rows, uint32_t* __restrict__ codes,
+__global__ __launch_bounds__(1024) void hash_hist_kernel(int64_t m, uint64_t s1, uint64_t seed, int64_t chunk_rows, uint32_t* __restrict__ codes,
                                                         uint32_t* __restrict__ hist, MemberStride ms) {
   __shared__ uint32_t lh[kHistLds];
   {
@@ -115,7 +115,7 @@ hipError_t launch_hash_hist(int64_t m, int64_t s1, uint64_t seed, int nchunk, ui
                             const MemberStride& ms) {
   if (m <= 0) return hipSuccess;
   if (ms.count < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(hash_hist_kernel, dim3(nchunk, ms.count), dim3(256), 0, s, m, (uint64_t)s1, seed, bucket_chunk_rows(m, nchunk), codes,
+  hipLaunchKernelGGL(hash_hist_kernel, dim3(nchunk, ms.count), dim3(1024), 0, s, m, (uint64_t)s1, seed, bucket_chunk_rows(m, nchunk), codes,
                      hist, ms);
   return hipGetLastError();
 }
@@ -310,7 +310,7 @@ bool bucket_scatter_sorts(int64_t s1) { return s1 <= (int64_t)kScatterLds; }
 // ascending row order.  A segment longer than the largest network flags its bucket for the
 // gather's own sort.  With the counters in global memory (s1 above the LDS limit) the
 // segments are left as they are and the gather sorts every bucket.
-__global__ __launch_bounds__(256) void bucket_scatter_kernel(int64_t m, int64_t s1, int64_t chunk_rows, const uint32_t* __restrict__ codes,
+__global__ __launch_bounds__(1024) void bucket_scatter_kernel(int64_t m, int64_t s1, int64_t chunk_rows, const uint32_t* __restrict__ codes,
                                                              const uint32_t* __restrict__ offsets, uint32_t* __restrict__ hist,
                                                              uint32_t* entries, uint8_t* __restrict__ unsorted, MemberStride ms) {
   __shared__ uint32_t cur[kScatterLds];
@@ -373,7 +373,10 @@ hipError_t launch_bucket_scatter(int64_t m, int64_t s1, int nchunk, const uint32
                                  uint32_t* entries, uint8_t* unsorted, hipStream_t s, const MemberStride& ms) {
   if (m <= 0) return hipSuccess;
   if ((bucket_scatter_sorts(s1) && unsorted == nullptr) || ms.count < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(bucket_scatter_kernel, dim3(nchunk, ms.count), dim3(256), 0, s, m, s1, bucket_chunk_rows(m, nchunk), codes, offsets,
+  // 16 waves per chunk with the counters in LDS (the chunk is one workgroup per CU); four with
+  // global counters, whose atomics contend more with more waves (measured 99 -> 130 us at s1 = 32768)
+  const int threads = bucket_scatter_sorts(s1) ? 1024 : 256;
+  hipLaunchKernelGGL(bucket_scatter_kernel, dim3(nchunk, ms.count), dim3(threads), 0, s, m, s1, bucket_chunk_rows(m, nchunk), codes, offsets,
                      hist, entries, unsorted, ms);
   return hipGetLastError();
 }
