@@ -121,11 +121,11 @@ hipError_t launch_hash_hist(int64_t m, int64_t s1, uint64_t seed, int nchunk, ui
 }
 
 // hist[chunk][b] <- rows of bucket b in earlier chunks (exclusive scan down each column);
-// counts[b] <- total rows of bucket b.  Workgroup: 32 buckets x 8 chunk segments; each thread
+// counts[b] <- total rows of bucket b.  Workgroup: 32 buckets x 16 chunk segments; each thread
 // scans its segment of one column, the segment totals are combined through LDS.
-__global__ __launch_bounds__(256) void hist_colscan_kernel(int nchunk, int64_t s1, uint32_t* __restrict__ hist, uint32_t* __restrict__ counts,
+__global__ __launch_bounds__(512) void hist_colscan_kernel(int nchunk, int64_t s1, uint32_t* __restrict__ hist, uint32_t* __restrict__ counts,
                                                            uint8_t* __restrict__ unsorted, MemberStride ms) {
-  constexpr int NB = 32, NS = 8, BATCH = 8;
+  constexpr int NB = 32, NS = 16, BATCH = 8;
   {
     const int64_t off = (int64_t)blockIdx.y * ms.ws;  // batch member
     hist = member_ptr(hist, off);
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(256) void hist_colscan_kernel(int nchunk, int64_t s
 hipError_t launch_hist_colscan(int nchunk, int64_t s1, uint32_t* hist, uint32_t* counts, uint8_t* unsorted, hipStream_t s,
                                const MemberStride& ms) {
   if (ms.count < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(hist_colscan_kernel, dim3((unsigned)((s1 + 31) / 32), ms.count), dim3(256), 0, s, nchunk, s1, hist, counts, unsorted,
+  hipLaunchKernelGGL(hist_colscan_kernel, dim3((unsigned)((s1 + 31) / 32), ms.count), dim3(512), 0, s, nchunk, s1, hist, counts, unsorted,
                      ms);
   return hipGetLastError();
 }
